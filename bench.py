@@ -1,0 +1,175 @@
+"""MARS benchmark: spin-updates/s of whole solves on one MI355X.
+
+One step = one complete solve of the workload (initial draws, every
+temperature level and phase, rounding, exact energies, best-of-runs), with
+the instance already resident in HBM.  Prints one JSON line.
+
+Default workload: dense SK N=2000, J ~ N(0, 1/N) fp32, 4096 runs, 300
+geometric levels, 2 update phases per sweep (the shape of the paper's
+largest SK experiment).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "spin-updates/s (runs×N×steps) at equal best-energy gap; p50/p99 solve latency"
+PEAK = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s
+
+DESCRIPTION = {
+    "sk2000": "SK N=2000 J~N(0,1/N) fp32, 4096 runs, T0~U[0.25,1.5]*sigma, 300 geometric levels to 0.01*sigma, "
+              "2 phases",
+    "ea2d_L16": "2D +-J lattice 16x16 periodic, 1024 runs, T0~U[0.5,3], 300 geometric levels to 0.02, fp64",
+    "er800": "Erdos-Renyi N=800 p=0.06 +-1 weights (J=-w), 8192 runs, 300 levels, greedy-colour phases, fp32",
+    "er20000": "Erdos-Renyi N=20000 avg degree 4 +-1 weights (J=-w), 8192 runs, 300 levels, fp32",
+    "ea3d_L32": "3D +-J lattice 32^3 periodic, 2048 runs, 1000 levels, fp16 magnetisation storage",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, seed, budget_s=12.0):
+    """Time the CPU oracle (FP64, threads over runs) on a bounded sample of runs."""
+    from oracle import oracle as O
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    N = w.instance.N
+    sch = w.schedule.replace(precision="fp64") if w.schedule.precision != "fp64" else w.schedule
+    n = cores
+    total_runs, total_t, total_upd = 0, 0.0, 0
+    while True:
+        t0 = time.perf_counter()
+        r = O.solve(w.instance, w.runs, sch, seed, run_begin=total_runs, run_count=n, nthreads=cores)
+        dt = time.perf_counter() - t0
+        total_runs += n
+        total_t += dt
+        total_upd += int(r["sweeps"].sum()) * N
+        if total_t >= budget_s or total_runs >= w.runs:
+            break
+        # grow the sample towards the budget
+        n = max(cores, min(w.runs - total_runs, int(n * max(1.0, (budget_s - total_t) / max(dt, 1e-3)))))
+    return {"value": total_upd / total_t, "unit": "spin-updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d runs at full N=%d and full schedule, %.1f s" % (total_runs, w.runs, N, total_t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sk2000", choices=sorted(DESCRIPTION))
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (runs would shard by index "
+              "across GPUs; see the design notes).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1907_05124_amd import inputs as I
+    from paper_1907_05124_amd import mars as M
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = I.workload(args.workload, seed=args.seed)
+    N, R = w.instance.N, w.runs
+    log("workload", args.workload, "N=%d R=%d" % (N, R))
+    inst = M.Instance.from_inputs(w.instance)
+    stream = torch.cuda.current_stream()
+
+    def solve(sch):
+        return inst.solve_ex(R, sch, args.seed, want_best=True, sync=False, stream=stream)
+
+    for i in range(args.warmup):
+        solve(w.schedule)
+        torch.cuda.synchronize()
+        log("warmup", i + 1, "done")
+
+    # timed region: K whole solves, events on the library's stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        solve(w.schedule)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    ms = float(np.mean(step_ms))
+    log("timed %d steps: %.3f ms/step (wall %.3f s)" % (args.steps, ms, wall))
+
+    # the same solve once more with host results, for the update count and the summary
+    out = inst.solve_ex(R, w.schedule, args.seed, want_best=True, sync=True, stream=stream)
+    res = out["result"]
+    updates = int(res["spin_updates"])
+    value = updates / (ms * 1e-3)
+
+    # dominant kernel: the field product of one phase.  Its average launch time
+    # is the solve time minus a solve with no levels (draws, rounding, energy,
+    # best-of-runs), divided by the number of phase launches, all timed with
+    # events on the same stream.
+    roofline = None
+    if isinstance(w.instance, I.DenseInstance):
+        zero = w.schedule.replace(steps=0)
+        reps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        solve(zero)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            solve(zero)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        base_ms = e0.elapsed_time(e1) / reps
+        _, phases = inst.describe(w.schedule)
+        launches = w.schedule.steps * phases
+        per_launch_s = max(ms - base_ms, 1e-6) * 1e-3 / launches
+        # algorithmic flops of one phase launch: 2 * (rows of the phase) * N * R
+        flops = 2.0 * (N / phases) * N * R
+        achieved = flops / per_launch_s / 1e12
+        peak = PEAK["fp32_mfma"]
+        roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4), "traffic": None,
+                    "kernel": "k_dense_phase_f32", "launch_us": round(per_launch_s * 1e6, 3),
+                    "flops_per_launch": flops}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(w, args.seed)
+        log("cpu baseline", cpu)
+
+    dtype = {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "fp16": "f16-store/f32"}[w.schedule.precision]
+    line = {
+        "metric": METRIC, "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": args.workload, "description": DESCRIPTION[args.workload], "N": N, "runs": R,
+                   "levels": w.schedule.steps, "parallelism": "single GPU, runs batched"},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "result": {"best_energy": res["best_energy"], "best_energy_per_spin": res["best_energy"] / N,
+                   "mean_energy_per_spin": res["mean_energy"] / N, "hit_count": res["hit_count"]},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    inst.close()
+
+
+if __name__ == "__main__":
+    main()

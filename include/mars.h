@@ -1,0 +1,195 @@
+/*
+ * mars.h -- C interface of the MARS solver for AMD Instinct MI355X (gfx950).
+ *
+ * MARS (Mean-field Annealing from a Random State; Yavorsky, Markovich,
+ * Polyakov, Rubtsov, arXiv:1907.05124) runs many independent mean-field
+ * descents of an Ising problem, each from a random magnetisation and a random
+ * starting temperature, rounds each to spins and keeps the best (paper,
+ * section "Mean-field Annealing from Random State", Algorithm 1).
+ *
+ * Conventions used by every entry point:
+ *
+ *   Energy (eq. (2), ordered-pair double sum, minimisation sign):
+ *       E(s) = - sum_i sum_{j != i} J_ij s_i s_j - sum_i h_i s_i,   s_i = +-1.
+ *   A max-cut instance with edge weights w is passed as J = -w; its cut is
+ *   (sum_{i != j} w_ij - E)/4 (eq. (3)) when h = 0.
+ *   Local field and update of one magnetisation (Algorithm 1 with J = -J_paper):
+ *       Phi_i = sum_j J_ij m_j + h_i / 2,   m_i <- (1-g) m_i + g tanh(Phi_i / T),
+ *   with damping g = 1 for the paper's method.
+ *   Spins are updated phase by phase inside a sweep (dense: contiguous row
+ *   blocks [floor(bN/B), floor((b+1)N/B)); lattice: checkerboard; sparse:
+ *   greedy colouring in index order); MARS_JACOBI uses one phase holding all
+ *   spins (every spin sees the previous sweep's values).
+ *   Rounding: s_i = +1 if m_i >= 0, else -1.
+ *   Energies are exact: the sum of the terms is rounded once to double.
+ *   Best run: lowest energy, ties to the lowest run index.
+ *   Random draws: SplitMix64 output function of (seed + (c+1)*0x9E3779B97F4A7C15)
+ *   with counter c = (stream<<62)|(run<<32)|spin; stream 0 gives
+ *   m0 = (2k+1-2^24)*2^-24, stream 1 gives T0 = T_lo + (T_hi-T_lo)*(k*2^-24),
+ *   k = the output's top 24 bits.
+ *
+ * Layouts: magnetisations are spin-major N x R with runs contiguous
+ * (element (i, r) at i*R + r); per-run spin vectors are run-major R x N
+ * (element (r, i) at r*N + i).
+ *
+ * Errors: every entry point returns a mars_status; on error it writes no
+ * output and mars_last_error() holds a message for the calling thread.  The
+ * library never aborts or throws across this interface.
+ * Threads: calls on one instance are serialised by the library; distinct
+ * instances may be used concurrently.
+ */
+#ifndef MARS_H
+#define MARS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mars_instance mars_instance;
+
+typedef enum {
+    MARS_OK = 0,
+    MARS_E_ARG = 1,          /* null pointer, bad size or bad schedule field */
+    MARS_E_ASYMMETRIC = 2,   /* J_ij != J_ji (bitwise) */
+    MARS_E_DIAGONAL = 3,     /* nonzero J_ii, or a self loop in CSR */
+    MARS_E_NONFINITE = 4,    /* NaN or infinity in J or h */
+    MARS_E_RANGE = 5,        /* exact energy would need more than 126 bits */
+    MARS_E_OOM = 6,          /* device allocation failed */
+    MARS_E_DEVICE = 7,       /* HIP runtime error or no usable gfx950 device */
+    MARS_E_UNSUPPORTED = 8   /* valid request outside what this build implements */
+} mars_status;
+
+enum { MARS_GEOMETRIC = 0, MARS_LINEAR = 1 };
+enum { MARS_PHASED = 0, MARS_JACOBI = 1 };
+enum { MARS_FP32 = 0, MARS_FP64 = 1, MARS_BF16 = 2, MARS_FP16 = 3 };
+
+/* Annealing schedule (Algorithm 1; parameters of section "Parameter settings").
+ *   kind        MARS_LINEAR: T <- T0, then T <- T - c_step before each level,
+ *               stopping at T <= 0 (the paper's scheduler).
+ *               MARS_GEOMETRIC: `steps` levels T_k = T0 exp((k/(steps-1)) ln(T_end/T0)).
+ *   T_lo, T_hi  range of the random starting temperature T0 (T_lo <= T_hi).
+ *   T_end       last geometric level (> 0).
+ *   c_step      linear decrement (> 0; the paper uses 1).
+ *   steps       number of geometric levels (>= 0).
+ *   max_sweeps  sweeps allowed per level (>= 1); a level also ends when the
+ *               largest change of a sweep is below d_min (the paper: 1e-4).
+ *               max_sweeps = 1 gives exactly one sweep per level.
+ *   update      MARS_PHASED or MARS_JACOBI.
+ *   phases      dense row blocks per sweep (>= 1; ignored for lattices/CSR).
+ *   damping     g in (0, 1]; 1 is the paper's update.
+ *   precision   MARS_FP32 (dense, lattice, CSR), MARS_FP64 (lattice, CSR),
+ *               MARS_FP16 (fp16 magnetisation storage, fp32 arithmetic;
+ *               lattice, CSR), MARS_BF16 (bf16 couplings and magnetisations
+ *               with fp32 accumulation; dense).
+ *   first_level, level_count
+ *               relax only levels [first_level, first_level+level_count) of
+ *               each run's schedule (level_count < 0: to the end).  With m0
+ *               and T0 supplied this resumes a solve from a saved state. */
+typedef struct {
+    int32_t kind;
+    double T_lo, T_hi, T_end, c_step;
+    int32_t steps;
+    int32_t max_sweeps;
+    double d_min;
+    int32_t update;
+    int32_t phases;
+    double damping;
+    int32_t precision;
+    int32_t first_level;
+    int32_t level_count;
+} mars_schedule;
+
+/* Summary of a solve (section "Ground state of Sherrington-Kirkpatrick
+ * spin-glass": best energy, mean energy, hit count, success probability). */
+typedef struct {
+    double best_energy;      /* lowest exact energy over the runs */
+    double best_cut;         /* (sum_{i!=j} -J_ij - best_energy)/4 (max-cut value if J = -w, h = 0) */
+    double mean_energy;      /* mean of the runs' exact energies */
+    double best_T0;          /* starting temperature of the best run */
+    int32_t best_run;        /* index of the best run (lowest index on ties) */
+    int32_t runs;
+    int64_t hit_count;       /* runs whose energy equals best_energy */
+    int64_t sweeps_executed; /* sweeps summed over runs */
+    int64_t spin_updates;    /* N x sweeps_executed: magnetisation recomputations */
+    int64_t cap_hits;        /* levels ended by max_sweeps (> 1) with d >= d_min */
+    int64_t levels_executed; /* levels summed over runs */
+} mars_result;
+
+/* Create a dense instance (paper eq. (2); the SK model of the section "Ising
+ * Spin Glass Model").  J: host pointer to N*N float32, row-major, symmetric
+ * bitwise, zero diagonal.  h: host pointer to N float32, or NULL for h = 0.
+ * The inputs are copied; the caller keeps ownership.  Errors: MARS_E_ARG
+ * (N < 1, null J or out), MARS_E_NONFINITE, MARS_E_ASYMMETRIC,
+ * MARS_E_DIAGONAL, MARS_E_RANGE, MARS_E_OOM, MARS_E_DEVICE. */
+mars_status mars_create(const float *J, const float *h, int32_t N, mars_instance **out);
+
+/* Create a sparse instance with integer couplings (the max-cut graphs of the
+ * section "MAX-CUT", J = -w).  Host pointers: rowptr[N+1], col[nnz],
+ * val[nnz] with nnz = rowptr[N]; both directions of every edge stored with
+ * the same value, columns strictly increasing within a row, no self loops,
+ * val != 0.  h as in mars_create.  Copied; caller keeps ownership.
+ * Errors: MARS_E_ARG (bad pointers, sizes or ordering), MARS_E_ASYMMETRIC,
+ * MARS_E_DIAGONAL, MARS_E_NONFINITE, MARS_E_RANGE, MARS_E_OOM, MARS_E_DEVICE. */
+mars_status mars_create_csr(int32_t N, const int32_t *rowptr, const int32_t *col, const int8_t *val,
+                            const float *h, mars_instance **out);
+
+/* Create a periodic hypercubic lattice instance (Edwards-Anderson model,
+ * section "Ising Spin Glass Model").  dim = 2 or 3; L[dim] even sizes >= 4;
+ * site i = x0 + L0*(x1 + L1*x2); bond[a*N + i] (int8, +1 or -1) couples site i
+ * with its neighbour one step along axis a (periodic).  h as in mars_create.
+ * Host pointers, copied.  Errors: MARS_E_ARG, MARS_E_NONFINITE, MARS_E_RANGE,
+ * MARS_E_OOM, MARS_E_DEVICE. */
+mars_status mars_create_lattice(int32_t dim, const int32_t *L, const int8_t *bond, const float *h,
+                                mars_instance **out);
+
+/* Release an instance and its device memory.  NULL is ignored. */
+void mars_destroy(mars_instance *inst);
+
+/* Number of spins and of update phases per sweep for a schedule (host query). */
+mars_status mars_describe(const mars_instance *inst, const mars_schedule *sched, int32_t *N, int32_t *phases);
+
+/* Solve with host outputs (Algorithm 1 over `runs` independent runs, then
+ * best-of-runs selection).  best_spins: host int8[N] (may be NULL);
+ * energies: host double[runs] (may be NULL); res: host (may be NULL).
+ * Blocks until the results are on the host.  Errors: MARS_E_ARG (runs < 1,
+ * bad schedule), MARS_E_UNSUPPORTED (precision not available for this
+ * instance type, or the state does not fit the chosen kernel),
+ * MARS_E_OOM, MARS_E_DEVICE. */
+mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
+                       int8_t *best_spins, double *energies, mars_result *res);
+
+/* Solve with device buffers on a caller stream.  All array pointers are
+ * DEVICE pointers and may be NULL:
+ *   m0       [N x runs] initial magnetisations (double for MARS_FP64, float
+ *            otherwise); NULL draws them from the generator.
+ *   T0       [runs] double starting temperatures; NULL draws them.
+ *   T0_used  [runs] double: receives the starting temperatures of the solve.
+ *   m_final  [N x runs] final magnetisations (same element type as m0).
+ *   spins    [runs x N] int8 rounded spins of every run.
+ *   energies [runs] double exact energies.
+ *   best_spins [N] int8 spins of the best run.
+ * stream is a hipStream_t (NULL: the default stream).  When res (HOST) is
+ * non-NULL the call waits for the stream and fills it; otherwise it returns
+ * after enqueueing.  Device outputs are valid once the stream reaches the end
+ * of the enqueued work.  Errors as mars_solve. */
+mars_status mars_solve_ex(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
+                          const void *m0, const double *T0, double *T0_used, void *m_final, int8_t *spins,
+                          double *energies, int8_t *best_spins, mars_result *res, void *stream);
+
+/* Exact energies (eq. (2)) of R spin vectors.  spins: DEVICE int8 [R x N]
+ * (values +-1); energies: DEVICE double [R].  stream as in mars_solve_ex;
+ * the call returns after enqueueing.  Errors: MARS_E_ARG, MARS_E_DEVICE. */
+mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, double *energies, void *stream);
+
+/* Static description of a status code, and the last error message of the
+ * calling thread (empty if none).  Both strings stay owned by the library. */
+const char *mars_status_str(mars_status s);
+const char *mars_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MARS_H */

@@ -454,8 +454,8 @@ static void run_one(const orc_instance *in, const orc_schedule *sc, const int32_
             }
             ++sweeps;
         } while (!(d < sc->d_min) && sweeps < sc->max_sweeps);
-        if (!(d < sc->d_min))
-            ++cap;
+        if (sc->max_sweeps > 1 && !(d < sc->d_min))
+            ++cap; /* a level cut short by the sweep cap */
         st->sweeps += sweeps;
         st->levels += 1;
         st->last_T = T;

@@ -1,0 +1,479 @@
+// Dense couplings: the local fields of one update phase for a block of runs
+// are one product  Phi[P, runs] = J[P, :] * M[:, runs]  (Algorithm 1's
+// Phi_i = sum_j J_ij s_j for every spin i of the phase and every run), done
+// on the matrix cores, with the annealing update fused into the epilogue.
+//
+// State layout: M is [Np x ldm] fp32, row i = spin i, column r = run r (runs
+// contiguous); rows >= N and columns >= R are zero and never written.
+// A sweep ping-pongs between two such buffers: the phase with rows [p0, p1)
+// reads rows < p0 from `Mnew` (already updated in this sweep) and all other
+// rows from `Mold`, and writes its own rows to `Mnew`.  After the last phase
+// `Mnew` holds the whole new state.
+#include <cmath>
+
+#include "common_device.h"
+#include "mars_internal.h"
+
+namespace mars {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// initial state
+// ---------------------------------------------------------------------------
+
+__global__ void k_dense_init_state(uint64_t seed, int N, int R, int ldm, const float *m0, float *M)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = blockIdx.y;
+    if (r >= R)
+        return;
+    M[(size_t)i * ldm + r] = m0 ? m0[(size_t)i * R + r] : draw_m0(seed, r, i);
+}
+
+void launch_dense_init_state(uint64_t seed, int N, int R, int ldm, const float *m0, float *M, hipStream_t s)
+{
+    dim3 grid((R + 255) / 256, N);
+    k_dense_init_state<<<grid, 256, 0, s>>>(seed, N, R, ldm, m0, M);
+}
+
+// ---------------------------------------------------------------------------
+// one update phase: fp32 matrix-core product + fused tanh update
+// ---------------------------------------------------------------------------
+//
+// Workgroup tile: 128 spins (rows of the phase) x 128 runs, K (all N spins)
+// streamed in slabs of 32.  Four waves in a 2 x 2 arrangement, each owning a
+// 64 x 64 sub-tile = 2 x 2 blocks of the 32x32x2 fp32 MFMA.  J is symmetric,
+// so the slab J[k0:k0+32, i0:i0+128] read row-wise is the transposed A tile:
+// both operands arrive as [k][128] rows with coalesced 16-byte loads and sit
+// in LDS k-major, where each MFMA operand read is 64 consecutive floats.
+// Slabs are double buffered: the loads of slab t+1 are in flight while the
+// matrix cores work on slab t.
+
+constexpr int DBM = 128, DBN = 128, DBK = 32, DNT = 256;
+
+__global__ __launch_bounds__(DNT) void k_dense_phase_f32(const float *__restrict__ J, int ldj,
+                                                         const float *__restrict__ Mold, float *__restrict__ Mnew,
+                                                         int ldm, int R, int p0, int p1, int a0, int nrt, int nct,
+                                                         int kpad, const float *__restrict__ invT,
+                                                         const float *__restrict__ hhalf, float gamma,
+                                                         uint32_t *__restrict__ dmax)
+{
+    __shared__ float As[2][DBK][DBM];
+    __shared__ float Bs[2][DBK][DBN];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    // Tiles are ordered so that the 32 workgroups resident on one XCD (the
+    // hardware deals workgroups round-robin over the 8 XCDs) share a band of
+    // run columns: each XCD's L2 then holds its own slice of M plus the
+    // phase's J rows, instead of every XCD streaming all of M.
+    const int total = nrt * nct;
+    int t = blockIdx.x;
+    if ((total & 7) == 0)
+        t = (t & 7) * (total >> 3) + (t >> 3);
+    const int rt = t % nrt, ct = t / nrt;
+    const int i0 = a0 + rt * DBM;
+    const int c0 = ct * DBN;
+
+    floatx16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
+
+    const int lrow = tid >> 5;        // 0..7
+    const int lcol = (tid & 31) * 4;  // 0..124
+    float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+
+    // four 16-byte loads per operand per thread, held in named registers
+#define DENSE_GLOAD(k0)                                                                                 \
+    do {                                                                                                \
+        const int r0_ = (k0) + lrow;                                                                    \
+        const float *j_ = J + (size_t)r0_ * ldj + i0 + lcol;                                            \
+        ra0 = *reinterpret_cast<const float4 *>(j_);                                                    \
+        ra1 = *reinterpret_cast<const float4 *>(j_ + (size_t)8 * ldj);                                  \
+        ra2 = *reinterpret_cast<const float4 *>(j_ + (size_t)16 * ldj);                                 \
+        ra3 = *reinterpret_cast<const float4 *>(j_ + (size_t)24 * ldj);                                 \
+        rb0 = *reinterpret_cast<const float4 *>(((r0_ < p0) ? Mnew : Mold) + (size_t)r0_ * ldm + c0 + lcol);           \
+        rb1 = *reinterpret_cast<const float4 *>(((r0_ + 8 < p0) ? Mnew : Mold) + (size_t)(r0_ + 8) * ldm + c0 + lcol); \
+        rb2 = *reinterpret_cast<const float4 *>(((r0_ + 16 < p0) ? Mnew : Mold) + (size_t)(r0_ + 16) * ldm + c0 + lcol); \
+        rb3 = *reinterpret_cast<const float4 *>(((r0_ + 24 < p0) ? Mnew : Mold) + (size_t)(r0_ + 24) * ldm + c0 + lcol); \
+    } while (0)
+#define DENSE_SSTORE(buf)                                                                               \
+    do {                                                                                                \
+        *reinterpret_cast<float4 *>(&As[(buf)][lrow][lcol]) = ra0;                                      \
+        *reinterpret_cast<float4 *>(&As[(buf)][lrow + 8][lcol]) = ra1;                                  \
+        *reinterpret_cast<float4 *>(&As[(buf)][lrow + 16][lcol]) = ra2;                                 \
+        *reinterpret_cast<float4 *>(&As[(buf)][lrow + 24][lcol]) = ra3;                                 \
+        *reinterpret_cast<float4 *>(&Bs[(buf)][lrow][lcol]) = rb0;                                      \
+        *reinterpret_cast<float4 *>(&Bs[(buf)][lrow + 8][lcol]) = rb1;                                  \
+        *reinterpret_cast<float4 *>(&Bs[(buf)][lrow + 16][lcol]) = rb2;                                 \
+        *reinterpret_cast<float4 *>(&Bs[(buf)][lrow + 24][lcol]) = rb3;                                 \
+    } while (0)
+
+    const int nk = kpad / DBK;
+    DENSE_GLOAD(0);
+    DENSE_SSTORE(0);
+    __syncthreads();
+
+    const int ka = lane >> 5;  // which k of the pair this lane supplies
+    const int li = lane & 31;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) {
+            DENSE_GLOAD((kt + 1) * DBK);
+        }
+#pragma unroll
+        for (int kk = 0; kk < DBK / 2; ++kk) {
+            const int kr = 2 * kk + ka;
+            const float a0v = As[cur][kr][wm * 64 + li];
+            const float a1v = As[cur][kr][wm * 64 + 32 + li];
+            const float b0v = Bs[cur][kr][wn * 64 + li];
+            const float b1v = Bs[cur][kr][wn * 64 + 32 + li];
+            acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0v, b0v, acc00, 0, 0, 0);
+            acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0v, b1v, acc01, 0, 0, 0);
+            acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1v, b0v, acc10, 0, 0, 0);
+            acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1v, b1v, acc11, 0, 0, 0);
+        }
+        if (kt + 1 < nk) {
+            DENSE_SSTORE(cur ^ 1);
+        }
+        __syncthreads();
+    }
+
+    // Epilogue (Algorithm 1 with the interface's sign: m = tanh(Phi / T)).
+    // 32x32 MFMA result layout: lane l holds column l%32; register v holds row
+    // 8*(v/4) + 4*(l/32) + v%4 of the 32 x 32 block.
+    const bool damp = gamma != 1.0f;
+    auto epilogue = [&](const floatx16 acc, int mi, int nj) -> float {
+        const int col = c0 + wn * 64 + nj * 32 + li;
+        if (col >= R)
+            return 0.0f;
+        const float it = invT[col];
+        float dl = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = i0 + wm * 64 + mi * 32 + 8 * (v >> 2) + 4 * ka + (v & 3);
+            if (row >= p0 && row < p1) {
+                const size_t off = (size_t)row * ldm + col;
+                const float old = Mold[off];
+                float nw = old;
+                if (it >= 0.0f) {
+                    float phi = acc[v];
+                    if (hhalf)
+                        phi += hhalf[row];
+                    const float th = tanhf(phi * it);
+                    nw = damp ? (1.0f - gamma) * old + gamma * th : th;
+                }
+                Mnew[off] = nw;
+                dl = fmaxf(dl, fabsf(nw - old));
+            }
+        }
+        return dl;
+    };
+#undef DENSE_GLOAD
+#undef DENSE_SSTORE
+    float dl0 = fmaxf(epilogue(acc00, 0, 0), epilogue(acc10, 1, 0));
+    float dl1 = fmaxf(epilogue(acc01, 0, 1), epilogue(acc11, 1, 1));
+    if (dmax) {
+        dl0 = fmaxf(dl0, __shfl_xor(dl0, 32));
+        dl1 = fmaxf(dl1, __shfl_xor(dl1, 32));
+        if (ka == 0) {
+            const int col0 = c0 + wn * 64 + li;
+            if (col0 < R)
+                atomicMax(&dmax[col0], __float_as_uint(dl0));
+            if (col0 + 32 < R)
+                atomicMax(&dmax[col0 + 32], __float_as_uint(dl1));
+        }
+    }
+}
+
+void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, int ldm, int R, int p0, int p1,
+                            const float *invT, float gamma, uint32_t *dmax, hipStream_t s)
+{
+    const int a0 = p0 & ~3;
+    const int nrt = (p1 - a0 + DBM - 1) / DBM;
+    const int nct = ldm / DBN;
+    const int kpad = (I.N + DBK - 1) / DBK * DBK;
+    k_dense_phase_f32<<<nrt * nct, DNT, 0, s>>>(I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT,
+                                                 I.has_h ? I.hhalf : nullptr, gamma, dmax);
+}
+
+// ---------------------------------------------------------------------------
+// rounding, output copies, run statistics
+// ---------------------------------------------------------------------------
+
+// s_i = +1 if m_i >= 0 else -1, written run-major; optional compact copy of m.
+__global__ void k_dense_round(const float *M, int ldm, int N, int R, int8_t *spins, float *m_final)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = blockIdx.y;
+    if (r >= R)
+        return;
+    float m = M[(size_t)i * ldm + r];
+    spins[(size_t)r * N + i] = (m >= 0.0f) ? 1 : -1;
+    if (m_final)
+        m_final[(size_t)i * R + r] = m;
+}
+
+void launch_dense_round(const float *M, int ldm, int N, int R, int8_t *spins, float *m_final, hipStream_t s)
+{
+    dim3 grid((R + 255) / 256, N);
+    k_dense_round<<<grid, 256, 0, s>>>(M, ldm, N, R, spins, m_final);
+}
+
+// one sweep per level: sweeps = levels = nlev, no cap hits
+__global__ void k_dense_runstat(int R, const int32_t *nlev, int64_t *runstat)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R)
+        return;
+    runstat[(size_t)r * 4 + 0] = nlev[r];
+    runstat[(size_t)r * 4 + 1] = nlev[r];
+    runstat[(size_t)r * 4 + 2] = 0;
+    runstat[(size_t)r * 4 + 3] = 0;
+}
+
+void launch_dense_runstat(int R, const int32_t *nlev, int64_t *runstat, hipStream_t s)
+{
+    k_dense_runstat<<<(R + 255) / 256, 256, 0, s>>>(R, nlev, runstat);
+}
+
+// ---------------------------------------------------------------------------
+// several sweeps per level (Algorithm 1's repeat-until): per-run level state
+// ---------------------------------------------------------------------------
+//
+// state[2r] = level index, state[2r+1] = sweeps done at this level (or -1
+// once the run has finished its levels).  invT_cur[r] is the inverse
+// temperature of the run's current level, -1 for a finished run (its
+// magnetisations are then left unchanged by the phase kernel).
+
+__global__ void k_dense_advance_init(int R, const float *table, const int32_t *nlev, float *invT_cur,
+                                     int32_t *state, int64_t *runstat, uint32_t *dmax)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R)
+        return;
+    const bool any = nlev[r] > 0;
+    invT_cur[r] = any ? table[r] : -1.0f;
+    state[2 * r] = 0;
+    state[2 * r + 1] = any ? 0 : -1;
+    runstat[(size_t)r * 4 + 0] = 0;
+    runstat[(size_t)r * 4 + 1] = 0;
+    runstat[(size_t)r * 4 + 2] = 0;
+    runstat[(size_t)r * 4 + 3] = 0;
+    dmax[r] = 0u;
+}
+
+void launch_dense_advance_init(int R, const float *table, const int32_t *nlev, float *invT_cur, int32_t *state,
+                               int64_t *runstat, uint32_t *dmax, hipStream_t s)
+{
+    k_dense_advance_init<<<(R + 255) / 256, 256, 0, s>>>(R, table, nlev, invT_cur, state, runstat, dmax);
+}
+
+// After a sweep: a level ends when the sweep's largest change d is below
+// d_min or after max_sweeps sweeps; the run then moves to its next level.
+__global__ void k_dense_advance(int R, const float *table, int ldt, const int32_t *nlev, int max_sweeps,
+                                double d_min, float *invT_cur, int32_t *state, int64_t *runstat, uint32_t *dmax,
+                                uint32_t *active)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R)
+        return;
+    int sw = state[2 * r + 1];
+    if (sw < 0)
+        return;
+    const float d = __uint_as_float(dmax[r]);
+    dmax[r] = 0u;
+    ++sw;
+    runstat[(size_t)r * 4 + 0] += 1;
+    const bool conv = (double)d < d_min;
+    if (conv || sw >= max_sweeps) {
+        if (!conv && max_sweeps > 1)
+            runstat[(size_t)r * 4 + 2] += 1;
+        runstat[(size_t)r * 4 + 1] += 1;
+        const int lv = state[2 * r] + 1;
+        state[2 * r] = lv;
+        sw = 0;
+        if (lv >= nlev[r]) {
+            sw = -1;
+            invT_cur[r] = -1.0f;
+        } else {
+            invT_cur[r] = table[(size_t)lv * ldt + r];
+        }
+    }
+    state[2 * r + 1] = sw;
+    if (sw >= 0)
+        atomicAdd(active, 1u);
+}
+
+void launch_dense_advance(int R, const float *table, int ldt, const int32_t *nlev, int max_sweeps, double d_min,
+                          float *invT_cur, int32_t *state, int64_t *runstat, uint32_t *dmax, uint32_t *active,
+                          hipStream_t s)
+{
+    k_dense_advance<<<(R + 255) / 256, 256, 0, s>>>(R, table, ldt, nlev, max_sweeps, d_min, invT_cur, state,
+                                                     runstat, dmax, active);
+}
+
+// ---------------------------------------------------------------------------
+// exact energies (eq. (2)) of run-major spins
+// ---------------------------------------------------------------------------
+//
+// Every coupling and field value is an integer multiple of 2^emin, so with
+// Jfix = J * 2^-emin the energy is -2^emin * sum_i s_i (sum_j Jfix_ij s_j +
+// hfix_i), an integer sum done exactly (64-bit rows when the bit budget
+// allows, 128-bit otherwise; 128-bit totals) and rounded once.
+
+__global__ void k_dense_fixpoint(const float *J, int ldj, int N, int emin, int64_t *Jfix)
+{
+    size_t n = (size_t)N * N;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        size_t i = e / N, j = e % N;
+        float v = (i == j) ? 0.0f : J[i * ldj + j];
+        Jfix[e] = (int64_t)ldexp((double)v, -emin);
+    }
+}
+
+void launch_dense_fixpoint(const Instance &I, hipStream_t s)
+{
+    k_dense_fixpoint<<<2048, 256, 0, s>>>(I.J, I.Np, I.N, I.emin, I.Jfix);
+}
+
+constexpr int ERB = 16;  // rows per workgroup
+
+template <typename Acc>
+__global__ __launch_bounds__(64) void k_dense_energy_rows(const int64_t *__restrict__ Jfix,
+                                                          const int64_t *__restrict__ hfix, int N,
+                                                          const int8_t *__restrict__ spins, int R,
+                                                          __int128 *__restrict__ partial)
+{
+    const int lane = threadIdx.x;
+    const int r = blockIdx.x * 64 + lane;
+    const int i0 = blockIdx.y * ERB;
+    const bool live = r < R;
+    const int8_t *s = spins + (size_t)(live ? r : 0) * N;
+    Acc phi[ERB];
+#pragma unroll
+    for (int ii = 0; ii < ERB; ++ii)
+        phi[ii] = 0;
+    for (int j = 0; j < N; ++j) {
+        const bool up = s[j] > 0;
+#pragma unroll
+        for (int ii = 0; ii < ERB; ++ii) {
+            const int i = i0 + ii;
+            const int64_t v = (i < N) ? Jfix[(size_t)i * N + j] : 0;
+            phi[ii] += up ? (Acc)v : -(Acc)v;
+        }
+    }
+    __int128 e = 0;
+#pragma unroll
+    for (int ii = 0; ii < ERB; ++ii) {
+        const int i = i0 + ii;
+        if (i < N) {
+            __int128 f = (__int128)phi[ii] + (hfix ? (__int128)hfix[i] : (__int128)0);
+            e += (s[i] > 0) ? f : -f;
+        }
+    }
+    if (live)
+        partial[(size_t)blockIdx.y * R + r] = e;
+}
+
+__global__ void k_energy_finish(const __int128 *partial, int nblk, int R, int emin, double *E)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R)
+        return;
+    __int128 t = 0;
+    for (int b = 0; b < nblk; ++b)
+        t += partial[(size_t)b * R + r];
+    E[r] = i128_to_double_scaled(-t, emin);
+}
+
+static void launch_dense_energy(const Instance &I, const int8_t *spins, int R, double *E, void *partial,
+                                hipStream_t s)
+{
+    const int nblk = (I.N + ERB - 1) / ERB;
+    dim3 grid((R + 63) / 64, nblk);
+    __int128 *part = reinterpret_cast<__int128 *>(partial);
+    if (I.wide)
+        k_dense_energy_rows<__int128><<<grid, 64, 0, s>>>(I.Jfix, I.has_h ? I.hfix : nullptr, I.N, spins, R, part);
+    else
+        k_dense_energy_rows<int64_t><<<grid, 64, 0, s>>>(I.Jfix, I.has_h ? I.hfix : nullptr, I.N, spins, R, part);
+    k_energy_finish<<<(R + 255) / 256, 256, 0, s>>>(part, nblk, R, I.emin, E);
+}
+
+// ---------------------------------------------------------------------------
+// exact energies for the sparse and lattice instances
+// ---------------------------------------------------------------------------
+
+constexpr int GENT = 256;
+
+__global__ __launch_bounds__(GENT) void k_graph_energy(int kind, int N, const int32_t *__restrict__ rowptr,
+                                                       const uint32_t *__restrict__ colval, int dim, int L0,
+                                                       int L1, int L2, const uint8_t *__restrict__ bondbits,
+                                                       const int64_t *__restrict__ hfix, int emin,
+                                                       const int8_t *__restrict__ spins, double *E)
+{
+    __shared__ long long red[GENT];
+    const int r = blockIdx.x;
+    const int8_t *s = spins + (size_t)r * N;
+    long long acc = 0;
+    const int shift = -emin;  // couplings are integers, emin <= 0
+    for (int i = threadIdx.x; i < N; i += GENT) {
+        long long phi = 0;
+        if (kind == KIND_CSR) {
+            for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+                uint32_t cv = colval[k];
+                int u = (int)(cv >> 8);
+                int v = (int)(int8_t)(cv & 0xff);
+                phi += (s[u] > 0) ? v : -v;
+            }
+        } else {
+            int x = i % L0, y = (i / L0) % L1, z = i / (L0 * L1);
+            uint8_t b = bondbits[i];
+            int nb[6];
+            nb[0] = i - x + (x + 1) % L0;
+            nb[1] = i - x + (x + L0 - 1) % L0;
+            nb[2] = i + ((y + 1) % L1 - y) * L0;
+            nb[3] = i + ((y + L1 - 1) % L1 - y) * L0;
+            nb[4] = i + ((z + 1) % L2 - z) * L0 * L1;
+            nb[5] = i + ((z + L2 - 1) % L2 - z) * L0 * L1;
+            for (int q = 0; q < 2 * dim; ++q) {
+                int v = (b >> q & 1) ? -1 : 1;
+                phi += (s[nb[q]] > 0) ? v : -v;
+            }
+        }
+        long long f = phi << shift;
+        if (hfix)
+            f += hfix[i];
+        acc += (s[i] > 0) ? f : -f;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = GENT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        E[r] = i128_to_double_scaled(-(__int128)red[0], emin);
+}
+
+size_t energy_partial_bytes(const Instance &I, int R)
+{
+    if (I.kind != KIND_DENSE)
+        return 16;
+    return (size_t)((I.N + ERB - 1) / ERB) * (size_t)R * sizeof(__int128);
+}
+
+void launch_energy_from_spins(const Instance &I, const int8_t *spins, int R, double *E, void *partial, hipStream_t s)
+{
+    if (I.kind == KIND_DENSE) {
+        launch_dense_energy(I, spins, R, E, partial, s);
+        return;
+    }
+    k_graph_energy<<<R, GENT, 0, s>>>(I.kind, I.N, I.rowptr, I.colval, I.dim, I.L[0], I.L[1], I.L[2], I.bondbits,
+                                      I.has_h ? I.hfix : nullptr, I.emin, spins, E);
+}
+
+}  // namespace mars

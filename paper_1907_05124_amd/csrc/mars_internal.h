@@ -1,0 +1,127 @@
+// Internal declarations of the MARS HIP library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mars.h"
+
+namespace mars {
+
+enum Kind { KIND_DENSE = 0, KIND_CSR = 1, KIND_LATTICE = 2 };
+
+// Device buffer owned by an instance; grows on demand, freed on destroy.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace {
+    DevBuf Ma, Mb;          // dense state ping-pong buffers [Np x ldm]
+    DevBuf invT;            // per-level per-run inverse temperatures
+    DevBuf T0;              // [R] double
+    DevBuf nlev;            // [R] int32 levels in range per run
+    DevBuf runstat;         // [R x 4] int64: sweeps, levels, cap hits, spare
+    DevBuf dmax;            // [R] uint32 (bit pattern of a non-negative float)
+    DevBuf spins;           // [R x N] int8
+    DevBuf energies;        // [R] double
+    DevBuf partial;         // dense energy partial sums
+    DevBuf result;          // device mars_result + best index
+    DevBuf runstate;        // paper mode per-run level state
+    DevBuf flag;            // small counters
+};
+
+struct Instance {
+    int kind = KIND_DENSE;
+    int N = 0;
+    int device = 0;
+    // fixed point used for exact energies: every coupling and field value is
+    // an integer multiple of 2^emin
+    int emin = 0;
+    int wide = 0;           // dense: row sums need 128-bit accumulators
+    double wsum = 0.0;      // sum_{i != j} -J_ij (for the cut value)
+    bool has_h = false;
+    // dense
+    int Np = 0;             // padded dimension of J and of the state rows
+    float *J = nullptr;     // [Np x Np] zero padded
+    uint16_t *Jbf = nullptr;  // [Np x Np] bf16 copy (created on first bf16 solve)
+    int64_t *Jfix = nullptr;  // [N x N] fixed-point couplings
+    float *hhalf = nullptr;   // [Np] h/2 (fp32), zero padded
+    double *hhalf64 = nullptr;  // [N] h/2 (fp64)
+    int64_t *hfix = nullptr;  // [N] fixed-point field
+    // csr
+    int nnz = 0;
+    int32_t *rowptr = nullptr;
+    uint32_t *colval = nullptr;   // (col << 8) | uint8(val)
+    int ncolours = 0;
+    int32_t *phase_ptr = nullptr; // [ncolours+1]
+    int32_t *phase_vert = nullptr;// [N] vertices sorted by colour
+    int maxdeg = 0;
+    std::vector<int32_t> h_phase_ptr;
+    // lattice
+    int dim = 0;
+    int L[3] = {1, 1, 1};
+    uint8_t *bondbits = nullptr;  // [N]: bit 2a set if J(v, v+e_a) < 0, bit 2a+1 if J(v, v-e_a) < 0
+    // runtime
+    hipStream_t own_stream = nullptr;
+    Workspace ws;
+    std::mutex mu;
+};
+
+// ---- error reporting -------------------------------------------------------
+mars_status set_error(mars_status s, const std::string &msg);
+mars_status hip_error(hipError_t e, const char *what);
+mars_status ensure(DevBuf &b, size_t bytes);
+
+#define MARS_HIP(call)                                   \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_error(e_, #call); \
+    } while (0)
+
+// ---- launchers (each defined next to its kernels) -------------------------
+// common
+void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+void launch_init_T0(uint64_t seed, int R, double T_lo, double T_hi, const double *T0_in, double *T0_out,
+                    hipStream_t s);
+void launch_level_table(const mars_schedule &sc, int R, const double *T0, int kmax, int ldt, float *invT32,
+                        double *invT64, int32_t *nlev, hipStream_t s);
+void launch_argmin(const double *E, const double *T0, const int64_t *runstat, int R, int N, double wsum,
+                   mars_result *res_dev, int32_t *best_dev, hipStream_t s);
+void launch_gather_best(const int8_t *spins, const int32_t *best_dev, int N, int8_t *out, hipStream_t s);
+void launch_energy_from_spins(const Instance &I, const int8_t *spins, int R, double *E, void *partial,
+                              hipStream_t s);
+size_t energy_partial_bytes(const Instance &I, int R);
+
+// dense
+void launch_dense_init_state(uint64_t seed, int N, int R, int ldm, const float *m0, float *M, hipStream_t s);
+void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, int ldm, int R, int p0, int p1,
+                            const float *invT, float gamma, uint32_t *dmax, hipStream_t s);
+void launch_dense_round(const float *M, int ldm, int N, int R, int8_t *spins, float *m_final, hipStream_t s);
+void launch_dense_runstat(int R, const int32_t *nlev, int64_t *runstat, hipStream_t s);
+void launch_dense_fixpoint(const Instance &I, hipStream_t s);
+void launch_dense_advance_init(int R, const float *table, const int32_t *nlev, float *invT_cur, int32_t *state,
+                               int64_t *runstat, uint32_t *dmax, hipStream_t s);
+void launch_dense_advance(int R, const float *table, int ldt, const int32_t *nlev, int max_sweeps, double d_min,
+                          float *invT_cur, int32_t *state, int64_t *runstat, uint32_t *dmax, uint32_t *active,
+                          hipStream_t s);
+
+// graph (lattice and csr): the whole anneal of a block of runs in LDS
+struct GraphSolve {
+    const mars_schedule *sc;
+    uint64_t seed;
+    int R;
+    const void *m0;
+    const double *T0;      // starting temperatures, filled before the launch
+    void *m_final;
+    int8_t *spins;
+    double *energies;
+    int64_t *runstat;      // [R x 4]
+};
+mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s);
+
+}  // namespace mars

@@ -1,0 +1,860 @@
+// Host runtime behind include/mars.h: input validation, device encodings of
+// an instance, workspace management and the order of kernel launches of a
+// solve.  No arithmetic of the method runs here; every step of a solve is a
+// kernel on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common_device.h"
+#include "mars_internal.h"
+
+namespace mars {
+
+static thread_local std::string g_last_error;
+
+mars_status set_error(mars_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+mars_status hip_error(hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return set_error(MARS_E_OOM, m);
+    return set_error(MARS_E_DEVICE, m);
+}
+
+mars_status ensure(DevBuf &b, size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 16;
+    if (b.bytes >= bytes)
+        return MARS_OK;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+        if (e != hipSuccess)
+            return hip_error(e, "hipFree");
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return hip_error(e, "hipMalloc workspace");
+    }
+    b.bytes = bytes;
+    return MARS_OK;
+}
+
+static void free_buf(DevBuf &b)
+{
+    if (b.p)
+        (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T>
+static mars_status dev_alloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0)
+        count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_error(e, "hipMalloc");
+    }
+    return MARS_OK;
+}
+
+static void destroy_instance(Instance *I)
+{
+    if (!I)
+        return;
+    (void)hipSetDevice(I->device);
+    if (I->own_stream)
+        (void)hipStreamSynchronize(I->own_stream);
+    void *ptrs[] = {I->J, I->Jbf, I->Jfix, I->hhalf, I->hhalf64, I->hfix, I->rowptr,
+                    I->colval, I->phase_ptr, I->phase_vert, I->bondbits};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFree(p);
+    Workspace &w = I->ws;
+    DevBuf *bufs[] = {&w.Ma, &w.Mb, &w.invT, &w.T0, &w.nlev, &w.runstat, &w.dmax, &w.spins,
+                      &w.energies, &w.partial, &w.result, &w.runstate, &w.flag};
+    for (DevBuf *b : bufs)
+        free_buf(*b);
+    if (I->own_stream)
+        (void)hipStreamDestroy(I->own_stream);
+    delete I;
+}
+
+// ---------------------------------------------------------------------------
+// fixed point for exact energies
+// ---------------------------------------------------------------------------
+
+// Exponent of the lowest set bit of a nonzero finite float.
+static int low_bit_exponent(float v)
+{
+    int e;
+    float f = std::frexp(std::fabs(v), &e);  // v = f * 2^e, f in [0.5, 1)
+    uint32_t m = (uint32_t)std::ldexp(f, 24);  // 24-bit integer mantissa (exact)
+    int tz = __builtin_ctz(m);
+    return e - 24 + tz;
+}
+
+static int high_bit_exponent(float v)
+{
+    int e;
+    (void)std::frexp(std::fabs(v), &e);
+    return e;  // |v| < 2^e
+}
+
+// Bit budget: every term is a multiple of 2^emin below 2^emax.  Row sums of
+// N terms need emax - emin + log2(N) bits; the total another log2(N).
+struct FixInfo {
+    int emin = 0, emax = -1000;
+    bool any = false;
+    void add(float v)
+    {
+        if (v == 0.0f)
+            return;
+        emin = any ? std::min(emin, low_bit_exponent(v)) : low_bit_exponent(v);
+        emax = any ? std::max(emax, high_bit_exponent(v)) : high_bit_exponent(v);
+        any = true;
+    }
+};
+
+static int ceil_log2(long long n)
+{
+    int b = 0;
+    while ((1ll << b) < n)
+        ++b;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// instance creation
+// ---------------------------------------------------------------------------
+
+static mars_status start_instance(Instance *I)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_error(e, "hipGetDevice");
+    I->device = dev;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess)
+        return hip_error(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(MARS_E_DEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+    e = hipStreamCreateWithFlags(&I->own_stream, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return hip_error(e, "hipStreamCreate");
+    return MARS_OK;
+}
+
+static mars_status check_h(const float *h, int N, FixInfo &fx)
+{
+    if (!h)
+        return MARS_OK;
+    for (int i = 0; i < N; ++i) {
+        if (!std::isfinite(h[i]))
+            return set_error(MARS_E_NONFINITE, "h contains a non-finite value");
+        fx.add(h[i]);
+    }
+    return MARS_OK;
+}
+
+static mars_status upload_h(Instance *I, const float *h, int padN)
+{
+    const int N = I->N;
+    I->has_h = false;
+    if (!h)
+        return MARS_OK;
+    bool any = false;
+    for (int i = 0; i < N; ++i)
+        any |= h[i] != 0.0f;
+    if (!any)
+        return MARS_OK;
+    I->has_h = true;
+    std::vector<float> hh((size_t)padN, 0.0f);
+    std::vector<double> hh64((size_t)N);
+    std::vector<int64_t> hf((size_t)N);
+    for (int i = 0; i < N; ++i) {
+        hh[i] = h[i] * 0.5f;  // exact: halving a float (normal range) is exact
+        hh64[i] = (double)h[i] * 0.5;
+        hf[i] = (int64_t)std::ldexp((double)h[i], -I->emin);
+    }
+    mars_status st;
+    if ((st = dev_alloc(&I->hhalf, (size_t)padN)) != MARS_OK)
+        return st;
+    if ((st = dev_alloc(&I->hhalf64, (size_t)N)) != MARS_OK)
+        return st;
+    if ((st = dev_alloc(&I->hfix, (size_t)N)) != MARS_OK)
+        return st;
+    MARS_HIP(hipMemcpy(I->hhalf, hh.data(), sizeof(float) * padN, hipMemcpyHostToDevice));
+    MARS_HIP(hipMemcpy(I->hhalf64, hh64.data(), sizeof(double) * N, hipMemcpyHostToDevice));
+    MARS_HIP(hipMemcpy(I->hfix, hf.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice));
+    return MARS_OK;
+}
+
+static mars_status create_dense(const float *J, const float *h, int N, Instance *I)
+{
+    I->kind = KIND_DENSE;
+    I->N = N;
+    FixInfo fx;
+    double wsum = 0.0;
+    for (long long i = 0; i < N; ++i) {
+        for (long long j = 0; j < N; ++j) {
+            float v = J[i * N + j];
+            if (!std::isfinite(v))
+                return set_error(MARS_E_NONFINITE, "J contains a non-finite value");
+        }
+    }
+    for (long long i = 0; i < N; ++i) {
+        if (J[i * N + i] != 0.0f)
+            return set_error(MARS_E_DIAGONAL, "J has a nonzero diagonal entry (the energy sums j != i)");
+        for (long long j = i + 1; j < N; ++j) {
+            float a = J[i * N + j], b = J[j * N + i];
+            uint32_t ua, ub;
+            std::memcpy(&ua, &a, 4);
+            std::memcpy(&ub, &b, 4);
+            if (ua != ub)
+                return set_error(MARS_E_ASYMMETRIC, "J is not symmetric (bitwise)");
+            fx.add(a);
+            wsum -= 2.0 * (double)a;
+        }
+    }
+    mars_status st = check_h(h, N, fx);
+    if (st != MARS_OK)
+        return st;
+    I->emin = fx.any ? fx.emin : 0;
+    const int bits = fx.any ? fx.emax - I->emin : 0;  // |fixed value| < 2^bits
+    if (bits > 62)
+        return set_error(MARS_E_RANGE, "coupling/field values span more than 62 bits of binary range");
+    const int lg = ceil_log2((long long)N + 1);
+    if (bits + 2 * lg + 2 > 126)
+        return set_error(MARS_E_RANGE, "exact energy would need more than 126 bits");
+    I->wide = (bits + lg + 1 > 62) ? 1 : 0;
+    I->wsum = wsum;
+    I->Np = ((N + 127) / 128) * 128 + 128;
+    const size_t Np = (size_t)I->Np;
+    if ((st = dev_alloc(&I->J, Np * Np)) != MARS_OK)
+        return st;
+    MARS_HIP(hipMemset(I->J, 0, sizeof(float) * Np * Np));
+    MARS_HIP(hipMemcpy2D(I->J, sizeof(float) * Np, J, sizeof(float) * N, sizeof(float) * N, N,
+                         hipMemcpyHostToDevice));
+    if ((st = dev_alloc(&I->Jfix, (size_t)N * N)) != MARS_OK)
+        return st;
+    launch_dense_fixpoint(*I, I->own_stream);
+    MARS_HIP(hipGetLastError());
+    if ((st = upload_h(I, h, I->Np)) != MARS_OK)
+        return st;
+    MARS_HIP(hipStreamSynchronize(I->own_stream));
+    return MARS_OK;
+}
+
+static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, const int8_t *val, const float *h,
+                              Instance *I)
+{
+    I->kind = KIND_CSR;
+    I->N = N;
+    if (rowptr[0] != 0)
+        return set_error(MARS_E_ARG, "rowptr[0] must be 0");
+    for (int i = 0; i < N; ++i)
+        if (rowptr[i + 1] < rowptr[i])
+            return set_error(MARS_E_ARG, "rowptr must be non-decreasing");
+    const long long nnz = rowptr[N];
+    if (nnz > 0 && (!col || !val))
+        return set_error(MARS_E_ARG, "col and val are required when nnz > 0");
+    if (N >= (1 << 24))
+        return set_error(MARS_E_UNSUPPORTED, "sparse instances are limited to N < 2^24");
+    FixInfo fx;
+    int maxdeg = 0;
+    double wsum = 0.0;
+    for (int i = 0; i < N; ++i) {
+        maxdeg = std::max(maxdeg, rowptr[i + 1] - rowptr[i]);
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int j = col[k];
+            if (j < 0 || j >= N)
+                return set_error(MARS_E_ARG, "column index out of range");
+            if (k > rowptr[i] && col[k - 1] >= j)
+                return set_error(MARS_E_ARG, "columns must be strictly increasing within a row");
+            if (j == i)
+                return set_error(MARS_E_DIAGONAL, "self loop in CSR");
+            if (val[k] == 0)
+                return set_error(MARS_E_ARG, "stored values must be nonzero");
+            // the mirror entry (j, i) must exist with the same value
+            const int32_t *b = col + rowptr[j], *e = col + rowptr[j + 1];
+            const int32_t *f = std::lower_bound(b, e, i);
+            if (f == e || *f != i || val[rowptr[j] + (f - b)] != val[k])
+                return set_error(MARS_E_ASYMMETRIC, "CSR couplings are not symmetric");
+            fx.add((float)val[k]);
+            wsum -= (double)val[k];
+        }
+    }
+    mars_status st = check_h(h, N, fx);
+    if (st != MARS_OK)
+        return st;
+    I->emin = fx.any ? std::min(0, fx.emin) : 0;
+    I->maxdeg = maxdeg;
+    I->wsum = wsum;
+    I->nnz = (int)nnz;
+    {
+        // energy accumulates in 64 bits: N * (maxdeg * 128 + max|h|) in units of 2^emin
+        const int bits = (fx.any ? fx.emax : 0) - I->emin + ceil_log2((long long)maxdeg + 2) + 1;
+        if (bits + ceil_log2((long long)N + 1) + 1 > 62)
+            return set_error(MARS_E_RANGE, "exact energy would overflow 64-bit accumulation");
+    }
+    // greedy colouring in index order: colour(v) = smallest colour not used by
+    // neighbours u < v; each colour class is one update phase
+    std::vector<int32_t> colour((size_t)N, 0);
+    std::vector<char> used((size_t)maxdeg + 2, 0);
+    int ncol = 1;
+    for (int v = 0; v < N; ++v) {
+        for (int k = rowptr[v]; k < rowptr[v + 1]; ++k)
+            if (col[k] < v && colour[col[k]] <= maxdeg)
+                used[colour[col[k]]] = 1;
+        int c = 0;
+        while (used[c])
+            ++c;
+        colour[v] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int k = rowptr[v]; k < rowptr[v + 1]; ++k)
+            if (col[k] < v && colour[col[k]] <= maxdeg)
+                used[colour[col[k]]] = 0;
+    }
+    std::vector<int32_t> pptr((size_t)ncol + 1, 0), pvert((size_t)N);
+    for (int v = 0; v < N; ++v)
+        ++pptr[colour[v] + 1];
+    for (int c = 0; c < ncol; ++c)
+        pptr[c + 1] += pptr[c];
+    {
+        std::vector<int32_t> fill(pptr.begin(), pptr.end() - 1);
+        for (int v = 0; v < N; ++v)
+            pvert[fill[colour[v]]++] = v;
+    }
+    I->ncolours = ncol;
+    I->h_phase_ptr = pptr;
+    std::vector<uint32_t> cv((size_t)std::max<long long>(nnz, 1));
+    for (long long k = 0; k < nnz; ++k)
+        cv[k] = ((uint32_t)col[k] << 8) | (uint32_t)(uint8_t)val[k];
+    if ((st = dev_alloc(&I->rowptr, (size_t)N + 1)) != MARS_OK)
+        return st;
+    if ((st = dev_alloc(&I->colval, cv.size())) != MARS_OK)
+        return st;
+    if ((st = dev_alloc(&I->phase_ptr, pptr.size())) != MARS_OK)
+        return st;
+    if ((st = dev_alloc(&I->phase_vert, (size_t)N)) != MARS_OK)
+        return st;
+    MARS_HIP(hipMemcpy(I->rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice));
+    MARS_HIP(hipMemcpy(I->colval, cv.data(), sizeof(uint32_t) * cv.size(), hipMemcpyHostToDevice));
+    MARS_HIP(hipMemcpy(I->phase_ptr, pptr.data(), sizeof(int32_t) * pptr.size(), hipMemcpyHostToDevice));
+    MARS_HIP(hipMemcpy(I->phase_vert, pvert.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice));
+    return upload_h(I, h, N);
+}
+
+static mars_status create_lattice(int dim, const int32_t *L, const int8_t *bond, const float *h, Instance *I)
+{
+    I->kind = KIND_LATTICE;
+    I->dim = dim;
+    long long N = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (L[a] < 4 || (L[a] & 1))
+            return set_error(MARS_E_ARG, "lattice sizes must be even and >= 4");
+        I->L[a] = L[a];
+        N *= L[a];
+    }
+    if (N >= (1ll << 30))
+        return set_error(MARS_E_ARG, "lattice too large");
+    if (I->L[0] > 2048)
+        return set_error(MARS_E_UNSUPPORTED, "lattice rows longer than 2048 sites");
+    I->N = (int)N;
+    FixInfo fx;
+    double wsum = 0.0;
+    for (long long k = 0; k < dim * N; ++k) {
+        if (bond[k] != 1 && bond[k] != -1)
+            return set_error(MARS_E_ARG, "lattice bonds must be +1 or -1");
+        fx.add((float)bond[k]);
+        wsum -= 2.0 * bond[k];
+    }
+    mars_status st = check_h(h, (int)N, fx);
+    if (st != MARS_OK)
+        return st;
+    I->emin = fx.any ? std::min(0, fx.emin) : 0;
+    I->maxdeg = 2 * dim;
+    I->wsum = wsum;
+    {
+        const int bits = (fx.any ? fx.emax : 0) - I->emin + 4;
+        if (bits + ceil_log2(N + 1) + 1 > 62)
+            return set_error(MARS_E_RANGE, "exact energy would overflow 64-bit accumulation");
+    }
+    // per site: bit 2a = coupling to +e_a is negative, bit 2a+1 = coupling to -e_a
+    std::vector<uint8_t> bits((size_t)N, 0);
+    const int L0 = I->L[0], L1 = I->L[1], L2 = dim == 3 ? I->L[2] : 1;
+    for (long long v = 0; v < N; ++v) {
+        int x = (int)(v % L0), y = (int)((v / L0) % L1), z = (int)(v / ((long long)L0 * L1));
+        long long mx = v - x + (x + L0 - 1) % L0;
+        long long my = v + (long long)((y + L1 - 1) % L1 - y) * L0;
+        long long mz = v + (long long)((z + L2 - 1) % L2 - z) * L0 * L1;
+        uint8_t b = 0;
+        if (bond[0 * N + v] < 0) b |= 1;
+        if (bond[0 * N + mx] < 0) b |= 2;
+        if (bond[1 * N + v] < 0) b |= 4;
+        if (bond[1 * N + my] < 0) b |= 8;
+        if (dim == 3) {
+            if (bond[2 * N + v] < 0) b |= 16;
+            if (bond[2 * N + mz] < 0) b |= 32;
+        }
+        bits[v] = b;
+    }
+    if ((st = dev_alloc(&I->bondbits, (size_t)N)) != MARS_OK)
+        return st;
+    MARS_HIP(hipMemcpy(I->bondbits, bits.data(), (size_t)N, hipMemcpyHostToDevice));
+    return upload_h(I, h, (int)N);
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+
+static mars_status check_schedule(const mars_schedule *s, int kind)
+{
+    if (!s)
+        return set_error(MARS_E_ARG, "schedule is NULL");
+    if (s->kind != MARS_GEOMETRIC && s->kind != MARS_LINEAR)
+        return set_error(MARS_E_ARG, "schedule.kind must be MARS_GEOMETRIC or MARS_LINEAR");
+    if (!std::isfinite(s->T_lo) || !std::isfinite(s->T_hi) || s->T_hi < s->T_lo || s->T_lo < 0.0)
+        return set_error(MARS_E_ARG, "need finite 0 <= T_lo <= T_hi");
+    if (s->kind == MARS_GEOMETRIC) {
+        if (!(s->T_lo > 0.0) || !(s->T_end > 0.0) || !std::isfinite(s->T_end))
+            return set_error(MARS_E_ARG, "geometric schedule needs T_lo > 0 and finite T_end > 0");
+        if (s->steps < 0)
+            return set_error(MARS_E_ARG, "steps must be >= 0");
+    } else {
+        if (!(s->c_step > 0.0) || !std::isfinite(s->c_step))
+            return set_error(MARS_E_ARG, "linear schedule needs c_step > 0");
+    }
+    if (s->max_sweeps < 1)
+        return set_error(MARS_E_ARG, "max_sweeps must be >= 1");
+    if (!(s->d_min >= 0.0))
+        return set_error(MARS_E_ARG, "d_min must be >= 0");
+    if (s->update != MARS_PHASED && s->update != MARS_JACOBI)
+        return set_error(MARS_E_ARG, "update must be MARS_PHASED or MARS_JACOBI");
+    if (kind == KIND_DENSE && s->update == MARS_PHASED && s->phases < 1)
+        return set_error(MARS_E_ARG, "phases must be >= 1");
+    if (!(s->damping > 0.0 && s->damping <= 1.0))
+        return set_error(MARS_E_ARG, "damping must be in (0, 1]");
+    if (s->first_level < 0)
+        return set_error(MARS_E_ARG, "first_level must be >= 0");
+    if (s->precision < MARS_FP32 || s->precision > MARS_FP16)
+        return set_error(MARS_E_ARG, "unknown precision");
+    return MARS_OK;
+}
+
+// Upper bound on the levels any run visits (table rows).
+static mars_status max_levels(const mars_schedule &sc, double Tmax, int *out)
+{
+    RunSchedule rs = make_run_schedule(sc);
+    if (sc.kind == MARS_GEOMETRIC) {
+        int stop = sc.steps;
+        if (sc.level_count >= 0 && rs.first + sc.level_count < stop)
+            stop = rs.first + sc.level_count;
+        *out = std::max(0, stop - rs.first);
+        return MARS_OK;
+    }
+    LevelWalker w;
+    w.start(rs, Tmax);
+    int n = 0;
+    while (!w.done) {
+        ++n;
+        if (n > 10000000)
+            return set_error(MARS_E_ARG, "linear schedule has more than 1e7 levels");
+        w.next(rs);
+    }
+    *out = n;
+    return MARS_OK;
+}
+
+static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const float *m0,
+                               const double *T0in, float *m_final, int8_t *spins, double *E, int8_t *best_spins,
+                               mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+{
+    if (sc.precision != MARS_FP32)
+        return set_error(MARS_E_UNSUPPORTED, "dense instances currently support MARS_FP32");
+    Workspace &w = I->ws;
+    const int N = I->N;
+    const int ldm = ((R + 127) / 128) * 128;
+    const size_t mbytes = sizeof(float) * (size_t)I->Np * ldm;
+    mars_status st;
+    if ((st = ensure(w.Ma, mbytes)) || (st = ensure(w.Mb, mbytes)) || (st = ensure(w.T0, sizeof(double) * R)) ||
+        (st = ensure(w.nlev, sizeof(int32_t) * R)) || (st = ensure(w.runstat, sizeof(int64_t) * 4 * R)) ||
+        (st = ensure(w.dmax, sizeof(uint32_t) * ldm)) || (st = ensure(w.runstate, sizeof(int32_t) * 4 * ldm)) ||
+        (st = ensure(w.flag, 64)))
+        return st;
+    float *Ma = (float *)w.Ma.p, *Mb = (float *)w.Mb.p;
+    launch_fill_u32((uint32_t *)Ma, 0u, mbytes / 4, s);
+    launch_fill_u32((uint32_t *)Mb, 0u, mbytes / 4, s);
+    double *T0 = (double *)w.T0.p;
+    launch_init_T0(seed, R, sc.T_lo, sc.T_hi, T0in, T0, s);
+    double Tmax = sc.T_hi;
+    if (T0in && sc.kind == MARS_LINEAR) {
+        std::vector<double> h((size_t)R);
+        MARS_HIP(hipMemcpyAsync(h.data(), T0in, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+        MARS_HIP(hipStreamSynchronize(s));
+        Tmax = *std::max_element(h.begin(), h.end());
+        if (!std::isfinite(Tmax))
+            return set_error(MARS_E_ARG, "T0 contains a non-finite value");
+    }
+    int kmax = 0;
+    if ((st = max_levels(sc, Tmax, &kmax)) != MARS_OK)
+        return st;
+    if ((st = ensure(w.invT, sizeof(float) * (size_t)std::max(kmax, 1) * ldm)) != MARS_OK)
+        return st;
+    float *table = (float *)w.invT.p;
+    int32_t *nlev = (int32_t *)w.nlev.p;
+    launch_level_table(sc, R, T0, kmax, ldm, table, nullptr, nlev, s);
+    launch_dense_init_state(seed, N, R, ldm, m0, Ma, s);
+
+    const int B = sc.update == MARS_JACOBI ? 1 : std::min(sc.phases, N);
+    std::vector<int> pb((size_t)B + 1);
+    for (int b = 0; b <= B; ++b)
+        pb[b] = (int)((long long)b * N / B);
+    const float gamma = (float)sc.damping;
+    float *cur = Ma, *nxt = Mb;
+    int64_t *runstat = (int64_t *)w.runstat.p;
+    if (sc.max_sweeps == 1) {
+        for (int k = 0; k < kmax; ++k) {
+            for (int b = 0; b < B; ++b)
+                if (pb[b + 1] > pb[b])
+                    launch_dense_phase_f32(*I, cur, nxt, ldm, R, pb[b], pb[b + 1], table + (size_t)k * ldm, gamma,
+                                           nullptr, s);
+            std::swap(cur, nxt);
+        }
+        launch_dense_runstat(R, nlev, runstat, s);
+    } else {
+        // several sweeps per level: per-run level state advanced on the device
+        float *invT_cur = (float *)w.runstate.p;  // [ldm] floats followed by [ldm x 2] ints
+        int32_t *state = (int32_t *)(invT_cur + ldm);
+        uint32_t *dmax = (uint32_t *)w.dmax.p;
+        uint32_t *active = (uint32_t *)w.flag.p;
+        launch_dense_advance_init(R, table, nlev, invT_cur, state, runstat, dmax, s);
+        const long long cap = (long long)kmax * sc.max_sweeps + 1;
+        long long done_sweeps = 0;
+        const int chunk = 8;
+        while (done_sweeps < cap) {
+            for (int c = 0; c < chunk; ++c) {
+                for (int b = 0; b < B; ++b)
+                    if (pb[b + 1] > pb[b])
+                        launch_dense_phase_f32(*I, cur, nxt, ldm, R, pb[b], pb[b + 1], invT_cur, gamma, dmax, s);
+                std::swap(cur, nxt);
+                launch_fill_u32(active, 0u, 1, s);
+                launch_dense_advance(R, table, ldm, nlev, sc.max_sweeps, sc.d_min, invT_cur, state, runstat, dmax,
+                                     active, s);
+                ++done_sweeps;
+            }
+            uint32_t h_active = 0;
+            MARS_HIP(hipMemcpyAsync(&h_active, active, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            MARS_HIP(hipStreamSynchronize(s));
+            if (h_active == 0)
+                break;
+        }
+    }
+    launch_dense_round(cur, ldm, N, R, spins, m_final, s);
+    launch_energy_from_spins(*I, spins, R, E, I->ws.partial.p, s);
+    launch_argmin(E, T0, runstat, R, N, I->wsum, res_dev, best_dev, s);
+    if (best_spins)
+        launch_gather_best(spins, best_dev, N, best_spins, s);
+    MARS_HIP(hipGetLastError());
+    return MARS_OK;
+}
+
+static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const void *m0,
+                               const double *T0in, void *m_final, int8_t *spins, double *E, int8_t *best_spins,
+                               mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+{
+    Workspace &w = I->ws;
+    mars_status st;
+    if ((st = ensure(w.T0, sizeof(double) * R)) || (st = ensure(w.runstat, sizeof(int64_t) * 4 * R)))
+        return st;
+    double *T0 = (double *)w.T0.p;
+    launch_init_T0(seed, R, sc.T_lo, sc.T_hi, T0in, T0, s);
+    GraphSolve g;
+    g.sc = &sc;
+    g.seed = seed;
+    g.R = R;
+    g.m0 = m0;
+    g.T0 = T0;
+    g.m_final = m_final;
+    g.spins = spins;
+    g.energies = E;
+    g.runstat = (int64_t *)w.runstat.p;
+    if ((st = launch_graph_solve(*I, g, s)) != MARS_OK)
+        return st;
+    launch_energy_from_spins(*I, spins, R, E, I->ws.partial.p, s);
+    launch_argmin(E, T0, g.runstat, R, I->N, I->wsum, res_dev, best_dev, s);
+    if (best_spins)
+        launch_gather_best(spins, best_dev, I->N, best_spins, s);
+    MARS_HIP(hipGetLastError());
+    return MARS_OK;
+}
+
+static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, uint64_t seed, const void *m0,
+                              const double *T0, void *m_final, int8_t *spins, double *E, int8_t *best_spins,
+                              mars_result *res, hipStream_t s)
+{
+    if (R < 1)
+        return set_error(MARS_E_ARG, "runs must be >= 1");
+    if (R >= (1 << 30))
+        return set_error(MARS_E_ARG, "runs must be < 2^30");
+    mars_status st = check_schedule(sched, I->kind);
+    if (st != MARS_OK)
+        return st;
+    MARS_HIP(hipSetDevice(I->device));
+    Workspace &w = I->ws;
+    const size_t spin_bytes = (size_t)R * I->N;
+    if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK)
+        return st;
+    if (!spins) {
+        if ((st = ensure(w.spins, spin_bytes)) != MARS_OK)
+            return st;
+        spins = (int8_t *)w.spins.p;
+    }
+    if (!E) {
+        if ((st = ensure(w.energies, sizeof(double) * R)) != MARS_OK)
+            return st;
+        E = (double *)w.energies.p;
+    }
+    if ((st = ensure(w.partial, energy_partial_bytes(*I, R))) != MARS_OK)
+        return st;
+    mars_result *res_dev = (mars_result *)w.result.p;
+    int32_t *best_dev = (int32_t *)((char *)w.result.p + sizeof(mars_result) + 16);
+    if (I->kind == KIND_DENSE)
+        st = solve_dense(I, R, *sched, seed, (const float *)m0, T0, (float *)m_final, spins, E, best_spins, res_dev,
+                         best_dev, s);
+    else
+        st = solve_graph(I, R, *sched, seed, m0, T0, m_final, spins, E, best_spins, res_dev, best_dev, s);
+    if (st != MARS_OK)
+        return st;
+    if (res) {
+        mars_result tmp;
+        MARS_HIP(hipMemcpyAsync(&tmp, res_dev, sizeof(mars_result), hipMemcpyDeviceToHost, s));
+        MARS_HIP(hipStreamSynchronize(s));
+        *res = tmp;
+    }
+    return MARS_OK;
+}
+
+}  // namespace mars
+
+// ---------------------------------------------------------------------------
+// C interface
+// ---------------------------------------------------------------------------
+
+using namespace mars;
+
+static mars_status finish_create(Instance *I, mars_status st, mars_instance **out)
+{
+    if (st != MARS_OK) {
+        destroy_instance(I);
+        return st;
+    }
+    *out = reinterpret_cast<mars_instance *>(I);
+    return MARS_OK;
+}
+
+extern "C" {
+
+mars_status mars_create(const float *J, const float *h, int32_t N, mars_instance **out)
+{
+    if (!out)
+        return set_error(MARS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!J || N < 1)
+        return set_error(MARS_E_ARG, "need J != NULL and N >= 1");
+    if (N > 200000)
+        return set_error(MARS_E_UNSUPPORTED, "dense N above 200000");
+    Instance *I = new (std::nothrow) Instance();
+    if (!I)
+        return set_error(MARS_E_OOM, "host allocation");
+    mars_status st = start_instance(I);
+    if (st == MARS_OK)
+        st = create_dense(J, h, N, I);
+    return finish_create(I, st, out);
+}
+
+mars_status mars_create_csr(int32_t N, const int32_t *rowptr, const int32_t *col, const int8_t *val, const float *h,
+                            mars_instance **out)
+{
+    if (!out)
+        return set_error(MARS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (N < 1 || !rowptr)
+        return set_error(MARS_E_ARG, "need N >= 1 and rowptr != NULL");
+    Instance *I = new (std::nothrow) Instance();
+    if (!I)
+        return set_error(MARS_E_OOM, "host allocation");
+    mars_status st = start_instance(I);
+    if (st == MARS_OK)
+        st = create_csr(N, rowptr, col, val, h, I);
+    return finish_create(I, st, out);
+}
+
+mars_status mars_create_lattice(int32_t dim, const int32_t *L, const int8_t *bond, const float *h,
+                                mars_instance **out)
+{
+    if (!out)
+        return set_error(MARS_E_ARG, "out is NULL");
+    *out = nullptr;
+    if ((dim != 2 && dim != 3) || !L || !bond)
+        return set_error(MARS_E_ARG, "need dim in {2, 3}, L and bond");
+    Instance *I = new (std::nothrow) Instance();
+    if (!I)
+        return set_error(MARS_E_OOM, "host allocation");
+    mars_status st = start_instance(I);
+    if (st == MARS_OK)
+        st = create_lattice(dim, L, bond, h, I);
+    return finish_create(I, st, out);
+}
+
+void mars_destroy(mars_instance *inst)
+{
+    if (inst)
+        destroy_instance(reinterpret_cast<Instance *>(inst));
+}
+
+mars_status mars_describe(const mars_instance *inst, const mars_schedule *sched, int32_t *N, int32_t *phases)
+{
+    if (!inst)
+        return set_error(MARS_E_ARG, "instance is NULL");
+    const Instance *I = reinterpret_cast<const Instance *>(inst);
+    if (N)
+        *N = I->N;
+    if (phases) {
+        int p;
+        if (sched && sched->update == MARS_JACOBI)
+            p = 1;
+        else if (I->kind == KIND_DENSE)
+            p = sched ? std::max(1, std::min(sched->phases, I->N)) : 1;
+        else if (I->kind == KIND_LATTICE)
+            p = 2;
+        else
+            p = I->ncolours;
+        *phases = p;
+    }
+    return MARS_OK;
+}
+
+mars_status mars_solve_ex(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
+                          const void *m0, const double *T0, double *T0_used, void *m_final, int8_t *spins,
+                          double *energies, int8_t *best_spins, mars_result *res, void *stream)
+{
+    if (!inst)
+        return set_error(MARS_E_ARG, "instance is NULL");
+    Instance *I = reinterpret_cast<Instance *>(inst);
+    std::lock_guard<std::mutex> lk(I->mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    mars_status st = solve_impl(I, runs, sched, seed, m0, T0, m_final, spins, energies, best_spins,
+                                T0_used ? nullptr : res, s);
+    if (st != MARS_OK || !T0_used)
+        return st;
+    MARS_HIP(hipMemcpyAsync(T0_used, I->ws.T0.p, sizeof(double) * runs, hipMemcpyDeviceToDevice, s));
+    if (res) {
+        mars_result tmp;
+        MARS_HIP(hipMemcpyAsync(&tmp, I->ws.result.p, sizeof(mars_result), hipMemcpyDeviceToHost, s));
+        MARS_HIP(hipStreamSynchronize(s));
+        *res = tmp;
+    }
+    return MARS_OK;
+}
+
+mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
+                       int8_t *best_spins, double *energies, mars_result *res)
+{
+    if (!inst)
+        return set_error(MARS_E_ARG, "instance is NULL");
+    Instance *I = reinterpret_cast<Instance *>(inst);
+    std::lock_guard<std::mutex> lk(I->mu);
+    if (runs < 1)
+        return set_error(MARS_E_ARG, "runs must be >= 1");
+    mars_status st = check_schedule(sched, I->kind);
+    if (st != MARS_OK)
+        return st;
+    MARS_HIP(hipSetDevice(I->device));
+    hipStream_t s = I->own_stream;
+    int8_t *dbest = nullptr;
+    double *dE = nullptr;
+    if (best_spins)
+        MARS_HIP(hipMalloc(&dbest, (size_t)I->N));
+    if (energies) {
+        hipError_t e = hipMalloc(&dE, sizeof(double) * runs);
+        if (e != hipSuccess) {
+            if (dbest)
+                (void)hipFree(dbest);
+            return hip_error(e, "hipMalloc energies");
+        }
+    }
+    mars_result tmp;
+    st = solve_impl(I, runs, sched, seed, nullptr, nullptr, nullptr, nullptr, dE, dbest, &tmp, s);
+    if (st == MARS_OK) {
+        hipError_t e = hipSuccess;
+        if (best_spins && e == hipSuccess)
+            e = hipMemcpy(best_spins, dbest, (size_t)I->N, hipMemcpyDeviceToHost);
+        if (energies && e == hipSuccess)
+            e = hipMemcpy(energies, dE, sizeof(double) * runs, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            st = hip_error(e, "copy results");
+        else if (res)
+            *res = tmp;
+    }
+    if (dbest)
+        (void)hipFree(dbest);
+    if (dE)
+        (void)hipFree(dE);
+    return st;
+}
+
+mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, double *energies, void *stream)
+{
+    if (!inst || !spins || !energies || R < 1)
+        return set_error(MARS_E_ARG, "need instance, spins, energies and R >= 1");
+    Instance *I = reinterpret_cast<Instance *>(inst);
+    std::lock_guard<std::mutex> lk(I->mu);
+    MARS_HIP(hipSetDevice(I->device));
+    mars_status st = ensure(I->ws.partial, energy_partial_bytes(*I, R));
+    if (st != MARS_OK)
+        return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    launch_energy_from_spins(*I, spins, R, energies, I->ws.partial.p, s);
+    MARS_HIP(hipGetLastError());
+    return MARS_OK;
+}
+
+const char *mars_status_str(mars_status s)
+{
+    switch (s) {
+    case MARS_OK: return "ok";
+    case MARS_E_ARG: return "invalid argument";
+    case MARS_E_ASYMMETRIC: return "couplings not symmetric";
+    case MARS_E_DIAGONAL: return "nonzero diagonal coupling";
+    case MARS_E_NONFINITE: return "non-finite input";
+    case MARS_E_RANGE: return "exact energy out of range";
+    case MARS_E_OOM: return "out of device memory";
+    case MARS_E_DEVICE: return "device error";
+    case MARS_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *mars_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
