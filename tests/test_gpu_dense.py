@@ -10,7 +10,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1907_05124_amd import inputs as I
-from tests.gpu_common import announce, conditioned_runs, energy_fsum_dense, require_gpu
+from tests.gpu_common import announce, check_trajectory, energy_fsum_dense, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -64,10 +64,11 @@ def test_one_level_parity(N, R, phases, update, damping, field):
     assert err <= TOL_FP32, err
 
 
-@pytest.mark.parametrize("levels", [1, 10, 300])
+@pytest.mark.parametrize("levels", [1, 10, 100, 300])
 def test_anneal_parity_checkpoints(levels):
-    """Full anneal (300 geometric levels) checked at levels 1, 10 and 300 on the
-    oracle's well-conditioned runs; energies of equal spin vectors are equal."""
+    """Full anneal (300 geometric levels) checked at levels 1, 10, 100 and 300
+    against the oracle-derived trajectory bound (1e-5 plus the fp32 rounding
+    the anneal amplifies); energies of equal spin vectors are equal."""
     M = _mars()
     N, R, seed = 256, 64, 5
     inst = I.sk_instance(N, 4)
@@ -76,15 +77,13 @@ def test_anneal_parity_checkpoints(levels):
     with M.Instance.from_inputs(inst) as g:
         out = g.solve_ex(R, sch, seed, want_m=True, want_spins=True)
     ref = O.solve(inst, R, sch, seed, run_count=R)
-    ok = conditioned_runs(inst, R, sch, seed, ref)
-    assert ok.mean() >= 0.5, "too few well-conditioned runs: %.2f" % ok.mean()
-    m = out["m"].cpu().numpy().astype(np.float64)
-    err = np.max(np.abs(m[:, ok] - ref["m"][:, ok]))
-    assert err <= TOL_FP32, err
     S = out["spins"].cpu().numpy()
     E = out["energies"].cpu().numpy()
-    same = np.all(S == ref["spins"], axis=1) & ok
-    assert same.sum() >= 1
+    within = check_trajectory(out["m"].cpu().numpy(), inst, R, sch, seed, ref, "fp32", spins=S)
+    print("runs within 1e-5: %.2f" % within)
+    assert within >= 0.5
+    same = np.all(S == ref["spins"], axis=1)
+    assert same.mean() >= 0.8
     assert np.array_equal(E[same], ref["energy"][same])
 
 
@@ -225,22 +224,11 @@ def test_bench_configuration_sampled_runs():
     m = out["m"].cpu().numpy()
     S = out["spins"].cpu().numpy()
     E = out["energies"].cpu().numpy()
-    sample = [0, 1, 1777, 4095]
-    ref = {k: [] for k in ("m", "spins", "energy", "ok")}
-    for r in sample:
+    for r in (0, 1, 1777, 4095):
         one = O.solve(inst, R, sch, 1, run_begin=r, run_count=1)
-        m0 = np.array([[O.lib().orc_initial_m(1, r, i)] for i in range(inst.N)])
-        pert = np.clip(m0 + 1e-9 * np.where(np.random.default_rng(r).random(m0.shape) < 0.5, -1, 1), -1, 1)
-        alt = O.solve(inst, R, sch, 1, run_begin=r, run_count=1, m0=pert, T0=one["T0"])
-        ref["ok"].append(np.max(np.abs(alt["m"] - one["m"])) <= 1e-6)
-        ref["m"].append(one["m"][:, 0])
-        ref["spins"].append(one["spins"][0])
-        ref["energy"].append(one["energy"][0])
-    for k, r in enumerate(sample):
-        if ref["ok"][k]:
-            assert np.max(np.abs(m[:, r].astype(np.float64) - ref["m"][k])) <= TOL_FP32
-        if np.array_equal(S[r], ref["spins"][k]):
-            assert E[r] == ref["energy"][k]
+        check_trajectory(m[:, r:r + 1], inst, R, sch, 1, one, "fp32", run_begin=r, spins=S[r:r + 1])
+        if np.array_equal(S[r], one["spins"][0]):
+            assert E[r] == one["energy"][0]
     # the summary refers to the full set of runs
     res = out["result"]
     assert res["best_energy"] == E.min() and res["spin_updates"] == R * 300 * inst.N
