@@ -64,6 +64,26 @@ def cpu_baseline(w, seed, budget_s=12.0):
             "sample": "%d of %d runs at full N=%d and full schedule, %.1f s" % (total_runs, w.runs, N, total_t)}
 
 
+def copy_calibration():
+    """One plain device-to-device copy of 256 MiB (after a warm-up copy): the
+    reference for scaling FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+
+    n = (256 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "ms": ms,
+                      "GB/s": 2 * n * 4 / ms / 1e6}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,7 +92,11 @@ def main():
     ap.add_argument("--workload", default="sk2000", choices=sorted(DESCRIPTION))
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (to scale rocprofv3 byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (runs would shard by index "
               "across GPUs; see the design notes).  Run with --gpus 1.", file=sys.stderr)

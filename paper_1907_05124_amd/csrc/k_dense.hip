@@ -12,11 +12,11 @@
 #include <cmath>
 
 #include "common_device.h"
+#include "dense_phase.h"
 #include "mars_internal.h"
 
 namespace mars {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
 // initial state
@@ -41,152 +41,10 @@ void launch_dense_init_state(uint64_t seed, int N, int R, int ldm, const float *
 // one update phase: fp32 matrix-core product + fused tanh update
 // ---------------------------------------------------------------------------
 //
-// Workgroup tile: 128 spins (rows of the phase) x 128 runs, K (all N spins)
-// streamed in slabs of 32.  Four waves in a 2 x 2 arrangement, each owning a
-// 64 x 64 sub-tile = 2 x 2 blocks of the 32x32x2 fp32 MFMA.  J is symmetric,
-// so the slab J[k0:k0+32, i0:i0+128] read row-wise is the transposed A tile:
-// both operands arrive as [k][128] rows with coalesced 16-byte loads and sit
-// in LDS k-major, where each MFMA operand read is 64 consecutive floats.
-// Slabs are double buffered: the loads of slab t+1 are in flight while the
-// matrix cores work on slab t.
-
-constexpr int DBM = 128, DBN = 128, DBK = 32, DNT = 256;
-
-__global__ __launch_bounds__(DNT) void k_dense_phase_f32(const float *__restrict__ J, int ldj,
-                                                         const float *__restrict__ Mold, float *__restrict__ Mnew,
-                                                         int ldm, int R, int p0, int p1, int a0, int nrt, int nct,
-                                                         int kpad, const float *__restrict__ invT,
-                                                         const float *__restrict__ hhalf, float gamma,
-                                                         uint32_t *__restrict__ dmax)
-{
-    __shared__ float As[2][DBK][DBM];
-    __shared__ float Bs[2][DBK][DBN];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-
-    // Tiles are ordered so that the 32 workgroups resident on one XCD (the
-    // hardware deals workgroups round-robin over the 8 XCDs) share a band of
-    // run columns: each XCD's L2 then holds its own slice of M plus the
-    // phase's J rows, instead of every XCD streaming all of M.
-    const int total = nrt * nct;
-    int t = blockIdx.x;
-    if ((total & 7) == 0)
-        t = (t & 7) * (total >> 3) + (t >> 3);
-    const int rt = t % nrt, ct = t / nrt;
-    const int i0 = a0 + rt * DBM;
-    const int c0 = ct * DBN;
-
-    floatx16 acc00 = {}, acc01 = {}, acc10 = {}, acc11 = {};
-
-    const int lrow = tid >> 5;        // 0..7
-    const int lcol = (tid & 31) * 4;  // 0..124
-    float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-
-    // four 16-byte loads per operand per thread, held in named registers
-#define DENSE_GLOAD(k0)                                                                                 \
-    do {                                                                                                \
-        const int r0_ = (k0) + lrow;                                                                    \
-        const float *j_ = J + (size_t)r0_ * ldj + i0 + lcol;                                            \
-        ra0 = *reinterpret_cast<const float4 *>(j_);                                                    \
-        ra1 = *reinterpret_cast<const float4 *>(j_ + (size_t)8 * ldj);                                  \
-        ra2 = *reinterpret_cast<const float4 *>(j_ + (size_t)16 * ldj);                                 \
-        ra3 = *reinterpret_cast<const float4 *>(j_ + (size_t)24 * ldj);                                 \
-        rb0 = *reinterpret_cast<const float4 *>(((r0_ < p0) ? Mnew : Mold) + (size_t)r0_ * ldm + c0 + lcol);           \
-        rb1 = *reinterpret_cast<const float4 *>(((r0_ + 8 < p0) ? Mnew : Mold) + (size_t)(r0_ + 8) * ldm + c0 + lcol); \
-        rb2 = *reinterpret_cast<const float4 *>(((r0_ + 16 < p0) ? Mnew : Mold) + (size_t)(r0_ + 16) * ldm + c0 + lcol); \
-        rb3 = *reinterpret_cast<const float4 *>(((r0_ + 24 < p0) ? Mnew : Mold) + (size_t)(r0_ + 24) * ldm + c0 + lcol); \
-    } while (0)
-#define DENSE_SSTORE(buf)                                                                               \
-    do {                                                                                                \
-        *reinterpret_cast<float4 *>(&As[(buf)][lrow][lcol]) = ra0;                                      \
-        *reinterpret_cast<float4 *>(&As[(buf)][lrow + 8][lcol]) = ra1;                                  \
-        *reinterpret_cast<float4 *>(&As[(buf)][lrow + 16][lcol]) = ra2;                                 \
-        *reinterpret_cast<float4 *>(&As[(buf)][lrow + 24][lcol]) = ra3;                                 \
-        *reinterpret_cast<float4 *>(&Bs[(buf)][lrow][lcol]) = rb0;                                      \
-        *reinterpret_cast<float4 *>(&Bs[(buf)][lrow + 8][lcol]) = rb1;                                  \
-        *reinterpret_cast<float4 *>(&Bs[(buf)][lrow + 16][lcol]) = rb2;                                 \
-        *reinterpret_cast<float4 *>(&Bs[(buf)][lrow + 24][lcol]) = rb3;                                 \
-    } while (0)
-
-    const int nk = kpad / DBK;
-    DENSE_GLOAD(0);
-    DENSE_SSTORE(0);
-    __syncthreads();
-
-    const int ka = lane >> 5;  // which k of the pair this lane supplies
-    const int li = lane & 31;
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) {
-            DENSE_GLOAD((kt + 1) * DBK);
-        }
-#pragma unroll
-        for (int kk = 0; kk < DBK / 2; ++kk) {
-            const int kr = 2 * kk + ka;
-            const float a0v = As[cur][kr][wm * 64 + li];
-            const float a1v = As[cur][kr][wm * 64 + 32 + li];
-            const float b0v = Bs[cur][kr][wn * 64 + li];
-            const float b1v = Bs[cur][kr][wn * 64 + 32 + li];
-            acc00 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0v, b0v, acc00, 0, 0, 0);
-            acc01 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0v, b1v, acc01, 0, 0, 0);
-            acc10 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1v, b0v, acc10, 0, 0, 0);
-            acc11 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1v, b1v, acc11, 0, 0, 0);
-        }
-        if (kt + 1 < nk) {
-            DENSE_SSTORE(cur ^ 1);
-        }
-        __syncthreads();
-    }
-
-    // Epilogue (Algorithm 1 with the interface's sign: m = tanh(Phi / T)).
-    // 32x32 MFMA result layout: lane l holds column l%32; register v holds row
-    // 8*(v/4) + 4*(l/32) + v%4 of the 32 x 32 block.
-    const bool damp = gamma != 1.0f;
-    auto epilogue = [&](const floatx16 acc, int mi, int nj) -> float {
-        const int col = c0 + wn * 64 + nj * 32 + li;
-        if (col >= R)
-            return 0.0f;
-        const float it = invT[col];
-        float dl = 0.0f;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int row = i0 + wm * 64 + mi * 32 + 8 * (v >> 2) + 4 * ka + (v & 3);
-            if (row >= p0 && row < p1) {
-                const size_t off = (size_t)row * ldm + col;
-                const float old = Mold[off];
-                float nw = old;
-                if (it >= 0.0f) {
-                    float phi = acc[v];
-                    if (hhalf)
-                        phi += hhalf[row];
-                    const float th = tanhf(phi * it);
-                    nw = damp ? (1.0f - gamma) * old + gamma * th : th;
-                }
-                Mnew[off] = nw;
-                dl = fmaxf(dl, fabsf(nw - old));
-            }
-        }
-        return dl;
-    };
-#undef DENSE_GLOAD
-#undef DENSE_SSTORE
-    float dl0 = fmaxf(epilogue(acc00, 0, 0), epilogue(acc10, 1, 0));
-    float dl1 = fmaxf(epilogue(acc01, 0, 1), epilogue(acc11, 1, 1));
-    if (dmax) {
-        dl0 = fmaxf(dl0, __shfl_xor(dl0, 32));
-        dl1 = fmaxf(dl1, __shfl_xor(dl1, 32));
-        if (ka == 0) {
-            const int col0 = c0 + wn * 64 + li;
-            if (col0 < R)
-                atomicMax(&dmax[col0], __float_as_uint(dl0));
-            if (col0 + 32 < R)
-                atomicMax(&dmax[col0 + 32], __float_as_uint(dl1));
-        }
-    }
-}
+// 16 waves (4 x 4) per 128 x 128 tile, each wave one 32 x 32 MFMA block, slab
+// loads issued two slabs ahead (the shape measured fastest for this problem:
+// four waves per SIMD keep the matrix pipe fed across LDS reads and barriers).
+constexpr int DWM = 4, DWN = 4, DPF = 2;
 
 void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, int ldm, int R, int p0, int p1,
                             const float *invT, float gamma, uint32_t *dmax, hipStream_t s)
@@ -195,8 +53,8 @@ void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, i
     const int nrt = (p1 - a0 + DBM - 1) / DBM;
     const int nct = ldm / DBN;
     const int kpad = (I.N + DBK - 1) / DBK * DBK;
-    k_dense_phase_f32<<<nrt * nct, DNT, 0, s>>>(I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT,
-                                                 I.has_h ? I.hhalf : nullptr, gamma, dmax);
+    k_dense_phase_f32<DWM, DWN, DPF><<<nrt * nct, 64 * DWM * DWN, 0, s>>>(
+        I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma, dmax);
 }
 
 // ---------------------------------------------------------------------------
