@@ -163,16 +163,16 @@ void launch_argmin(const double *E, const double *T0, const int64_t *runstat, in
     k_argmin<<<1, ARG_NT, 0, s>>>(E, T0, runstat, R, N, wsum, res_dev, best_dev);
 }
 
-__global__ void k_gather_best(const int8_t *spins, const int32_t *best, int N, int8_t *out)
+__global__ void k_gather_best(const int8_t *spins, int ld, const int32_t *best, int N, int8_t *out)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < N)
-        out[i] = spins[(size_t)(*best) * N + i];
+        out[i] = spins[(size_t)(*best) * ld + i];
 }
 
-void launch_gather_best(const int8_t *spins, const int32_t *best_dev, int N, int8_t *out, hipStream_t s)
+void launch_gather_best(const int8_t *spins, int ld, const int32_t *best_dev, int N, int8_t *out, hipStream_t s)
 {
-    k_gather_best<<<(N + 255) / 256, 256, 0, s>>>(spins, best_dev, N, out);
+    k_gather_best<<<(N + 255) / 256, 256, 0, s>>>(spins, ld, best_dev, N, out);
 }
 
 }  // namespace mars

@@ -61,23 +61,46 @@ void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, i
 // rounding, output copies, run statistics
 // ---------------------------------------------------------------------------
 
-// s_i = +1 if m_i >= 0 else -1, written run-major; optional compact copy of m.
-__global__ void k_dense_round(const float *M, int ldm, int N, int R, int8_t *spins, float *m_final)
+// s_i = +1 if m_i >= 0 else -1 (Algorithm 1's continuous spins rounded), written
+// to the zero-padded run-major operand of the energy product [ldr x Ke] and,
+// when requested, to the caller's [R x N] spins and [N x R] magnetisations.
+// A 64 x 64 tile goes through LDS so that both the spin-major reads and the
+// run-major writes are coalesced.
+__global__ __launch_bounds__(256) void k_dense_round(const float *M, int ldm, int N, int R, int Ke, int ldr,
+                                                     int8_t *spad, int8_t *spins, float *m_final)
 {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    int i = blockIdx.y;
-    if (r >= R)
-        return;
-    float m = M[(size_t)i * ldm + r];
-    spins[(size_t)r * N + i] = (m >= 0.0f) ? 1 : -1;
-    if (m_final)
-        m_final[(size_t)i * R + r] = m;
+    __shared__ int8_t t[64][65];
+    const int i0 = blockIdx.y * 64, r0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+    for (int y = ty; y < 64; y += 4) {
+        const int i = i0 + y, r = r0 + tx;
+        int8_t v = 0;
+        if (i < N && r < R) {
+            const float m = M[(size_t)i * ldm + r];
+            v = (m >= 0.0f) ? 1 : -1;
+            if (m_final)
+                m_final[(size_t)i * R + r] = m;
+        }
+        t[y][tx] = v;
+    }
+    __syncthreads();
+    for (int y = ty; y < 64; y += 4) {
+        const int r = r0 + y, i = i0 + tx;
+        if (r < ldr && i < Ke) {
+            const int8_t v = t[tx][y];
+            spad[(size_t)r * Ke + i] = v;
+            if (spins && r < R && i < N)
+                spins[(size_t)r * N + i] = v;
+        }
+    }
 }
 
-void launch_dense_round(const float *M, int ldm, int N, int R, int8_t *spins, float *m_final, hipStream_t s)
+void launch_dense_round(const float *M, int ldm, int N, int R, int Ke, int8_t *spad, int8_t *spins, float *m_final,
+                        hipStream_t s)
 {
-    dim3 grid((R + 255) / 256, N);
-    k_dense_round<<<grid, 256, 0, s>>>(M, ldm, N, R, spins, m_final);
+    const int ldr = (R + 127) / 128 * 128;
+    dim3 grid((ldr + 63) / 64, (Ke + 63) / 64);
+    k_dense_round<<<grid, 256, 0, s>>>(M, ldm, N, R, Ke, ldr, spad, spins, m_final);
 }
 
 // one sweep per level: sweeps = levels = nlev, no cap hits
@@ -177,10 +200,9 @@ void launch_dense_advance(int R, const float *table, int ldt, const int32_t *nle
 // exact energies (eq. (2)) of run-major spins
 // ---------------------------------------------------------------------------
 //
-// Every coupling and field value is an integer multiple of 2^emin, so with
-// Jfix = J * 2^-emin the energy is -2^emin * sum_i s_i (sum_j Jfix_ij s_j +
-// hfix_i), an integer sum done exactly (64-bit rows when the bit budget
-// allows, 128-bit otherwise; 128-bit totals) and rounded once.
+// Every coupling and field value is an integer multiple of 2^emin; the dense
+// energy uses Jfix = J * 2^-emin, split into int8 digits whose products with
+// the spins run on the int8 matrix cores (k_energy.hip).
 
 __global__ void k_dense_fixpoint(const float *J, int ldj, int N, int emin, int64_t *Jfix)
 {
@@ -195,69 +217,6 @@ __global__ void k_dense_fixpoint(const float *J, int ldj, int N, int emin, int64
 void launch_dense_fixpoint(const Instance &I, hipStream_t s)
 {
     k_dense_fixpoint<<<2048, 256, 0, s>>>(I.J, I.Np, I.N, I.emin, I.Jfix);
-}
-
-constexpr int ERB = 16;  // rows per workgroup
-
-template <typename Acc>
-__global__ __launch_bounds__(64) void k_dense_energy_rows(const int64_t *__restrict__ Jfix,
-                                                          const int64_t *__restrict__ hfix, int N,
-                                                          const int8_t *__restrict__ spins, int R,
-                                                          __int128 *__restrict__ partial)
-{
-    const int lane = threadIdx.x;
-    const int r = blockIdx.x * 64 + lane;
-    const int i0 = blockIdx.y * ERB;
-    const bool live = r < R;
-    const int8_t *s = spins + (size_t)(live ? r : 0) * N;
-    Acc phi[ERB];
-#pragma unroll
-    for (int ii = 0; ii < ERB; ++ii)
-        phi[ii] = 0;
-    for (int j = 0; j < N; ++j) {
-        const bool up = s[j] > 0;
-#pragma unroll
-        for (int ii = 0; ii < ERB; ++ii) {
-            const int i = i0 + ii;
-            const int64_t v = (i < N) ? Jfix[(size_t)i * N + j] : 0;
-            phi[ii] += up ? (Acc)v : -(Acc)v;
-        }
-    }
-    __int128 e = 0;
-#pragma unroll
-    for (int ii = 0; ii < ERB; ++ii) {
-        const int i = i0 + ii;
-        if (i < N) {
-            __int128 f = (__int128)phi[ii] + (hfix ? (__int128)hfix[i] : (__int128)0);
-            e += (s[i] > 0) ? f : -f;
-        }
-    }
-    if (live)
-        partial[(size_t)blockIdx.y * R + r] = e;
-}
-
-__global__ void k_energy_finish(const __int128 *partial, int nblk, int R, int emin, double *E)
-{
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R)
-        return;
-    __int128 t = 0;
-    for (int b = 0; b < nblk; ++b)
-        t += partial[(size_t)b * R + r];
-    E[r] = i128_to_double_scaled(-t, emin);
-}
-
-static void launch_dense_energy(const Instance &I, const int8_t *spins, int R, double *E, void *partial,
-                                hipStream_t s)
-{
-    const int nblk = (I.N + ERB - 1) / ERB;
-    dim3 grid((R + 63) / 64, nblk);
-    __int128 *part = reinterpret_cast<__int128 *>(partial);
-    if (I.wide)
-        k_dense_energy_rows<__int128><<<grid, 64, 0, s>>>(I.Jfix, I.has_h ? I.hfix : nullptr, I.N, spins, R, part);
-    else
-        k_dense_energy_rows<int64_t><<<grid, 64, 0, s>>>(I.Jfix, I.has_h ? I.hfix : nullptr, I.N, spins, R, part);
-    k_energy_finish<<<(R + 255) / 256, 256, 0, s>>>(part, nblk, R, I.emin, E);
 }
 
 // ---------------------------------------------------------------------------
@@ -317,19 +276,8 @@ __global__ __launch_bounds__(GENT) void k_graph_energy(int kind, int N, const in
         E[r] = i128_to_double_scaled(-(__int128)red[0], emin);
 }
 
-size_t energy_partial_bytes(const Instance &I, int R)
+void launch_graph_energy(const Instance &I, const int8_t *spins, int R, double *E, hipStream_t s)
 {
-    if (I.kind != KIND_DENSE)
-        return 16;
-    return (size_t)((I.N + ERB - 1) / ERB) * (size_t)R * sizeof(__int128);
-}
-
-void launch_energy_from_spins(const Instance &I, const int8_t *spins, int R, double *E, void *partial, hipStream_t s)
-{
-    if (I.kind == KIND_DENSE) {
-        launch_dense_energy(I, spins, R, E, partial, s);
-        return;
-    }
     k_graph_energy<<<R, GENT, 0, s>>>(I.kind, I.N, I.rowptr, I.colval, I.dim, I.L[0], I.L[1], I.L[2], I.bondbits,
                                       I.has_h ? I.hfix : nullptr, I.emin, spins, E);
 }

@@ -27,7 +27,8 @@ struct Workspace {
     DevBuf nlev;            // [R] int32 levels in range per run
     DevBuf runstat;         // [R x 4] int64: sweeps, levels, cap hits, spare
     DevBuf dmax;            // [R] uint32 (bit pattern of a non-negative float)
-    DevBuf spins;           // [R x N] int8
+    DevBuf spins;           // [R x N] int8 (lattice/sparse)
+    DevBuf spad;            // dense: [ldr x Ke] int8 zero-padded run-major spins
     DevBuf energies;        // [R] double
     DevBuf partial;         // dense energy partial sums
     DevBuf result;          // device mars_result + best index
@@ -42,14 +43,16 @@ struct Instance {
     // fixed point used for exact energies: every coupling and field value is
     // an integer multiple of 2^emin
     int emin = 0;
-    int wide = 0;           // dense: row sums need 128-bit accumulators
     double wsum = 0.0;      // sum_{i != j} -J_ij (for the cut value)
     bool has_h = false;
     // dense
     int Np = 0;             // padded dimension of J and of the state rows
     float *J = nullptr;     // [Np x Np] zero padded
     uint16_t *Jbf = nullptr;  // [Np x Np] bf16 copy (created on first bf16 solve)
-    int64_t *Jfix = nullptr;  // [N x N] fixed-point couplings
+    int64_t *Jfix = nullptr;  // [N x N] fixed-point couplings (create-time only)
+    int8_t *Jlimb = nullptr;  // [nlimb x Me x Ke] balanced base-256 digits of Jfix
+    int nlimb = 0;
+    int Me = 0, Ke = 0;       // padded digit-matrix rows / columns (multiples of 128)
     float *hhalf = nullptr;   // [Np] h/2 (fp32), zero padded
     double *hhalf64 = nullptr;  // [N] h/2 (fp64)
     int64_t *hfix = nullptr;  // [N] fixed-point field
@@ -92,16 +95,21 @@ void launch_level_table(const mars_schedule &sc, int R, const double *T0, int km
                         double *invT64, int32_t *nlev, hipStream_t s);
 void launch_argmin(const double *E, const double *T0, const int64_t *runstat, int R, int N, double wsum,
                    mars_result *res_dev, int32_t *best_dev, hipStream_t s);
-void launch_gather_best(const int8_t *spins, const int32_t *best_dev, int N, int8_t *out, hipStream_t s);
-void launch_energy_from_spins(const Instance &I, const int8_t *spins, int R, double *E, void *partial,
-                              hipStream_t s);
-size_t energy_partial_bytes(const Instance &I, int R);
+void launch_gather_best(const int8_t *spins, int ld, const int32_t *best_dev, int N, int8_t *out, hipStream_t s);
+void launch_graph_energy(const Instance &I, const int8_t *spins, int R, double *E, hipStream_t s);
+// dense exact energy on the int8 matrix cores (k_energy.hip)
+void launch_dense_limbs(const Instance &I, hipStream_t s);
+size_t dense_spin_operand_bytes(const Instance &I, int R);
+void launch_pad_spins(const Instance &I, const int8_t *spins, int R, int8_t *Spad, hipStream_t s);
+size_t dense_energy_partial_bytes(const Instance &I, int R);
+void launch_dense_energy_i8(const Instance &I, const int8_t *Spad, int R, double *E, void *partial, hipStream_t s);
 
 // dense
 void launch_dense_init_state(uint64_t seed, int N, int R, int ldm, const float *m0, float *M, hipStream_t s);
 void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, int ldm, int R, int p0, int p1,
                             const float *invT, float gamma, uint32_t *dmax, hipStream_t s);
-void launch_dense_round(const float *M, int ldm, int N, int R, int8_t *spins, float *m_final, hipStream_t s);
+void launch_dense_round(const float *M, int ldm, int N, int R, int Ke, int8_t *spad, int8_t *spins, float *m_final,
+                        hipStream_t s);
 void launch_dense_runstat(int R, const int32_t *nlev, int64_t *runstat, hipStream_t s);
 void launch_dense_fixpoint(const Instance &I, hipStream_t s);
 void launch_dense_advance_init(int R, const float *table, const int32_t *nlev, float *invT_cur, int32_t *state,

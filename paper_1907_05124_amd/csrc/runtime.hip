@@ -80,13 +80,13 @@ static void destroy_instance(Instance *I)
     (void)hipSetDevice(I->device);
     if (I->own_stream)
         (void)hipStreamSynchronize(I->own_stream);
-    void *ptrs[] = {I->J, I->Jbf, I->Jfix, I->hhalf, I->hhalf64, I->hfix, I->rowptr,
+    void *ptrs[] = {I->J, I->Jbf, I->Jfix, I->Jlimb, I->hhalf, I->hhalf64, I->hfix, I->rowptr,
                     I->colval, I->phase_ptr, I->phase_vert, I->bondbits};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
     Workspace &w = I->ws;
-    DevBuf *bufs[] = {&w.Ma, &w.Mb, &w.invT, &w.T0, &w.nlev, &w.runstat, &w.dmax, &w.spins,
+    DevBuf *bufs[] = {&w.Ma, &w.Mb, &w.invT, &w.T0, &w.nlev, &w.runstat, &w.dmax, &w.spins, &w.spad,
                       &w.energies, &w.partial, &w.result, &w.runstate, &w.flag};
     for (DevBuf *b : bufs)
         free_buf(*b);
@@ -244,8 +244,10 @@ static mars_status create_dense(const float *J, const float *h, int N, Instance 
     const int lg = ceil_log2((long long)N + 1);
     if (bits + 2 * lg + 2 > 126)
         return set_error(MARS_E_RANGE, "exact energy would need more than 126 bits");
-    I->wide = (bits + lg + 1 > 62) ? 1 : 0;
     I->wsum = wsum;
+    // balanced base-256 digits: L digits cover |v| < 2^(8L-1)
+    I->nlimb = std::max(1, (bits + 1 + 7) / 8);
+    I->Me = I->Ke = ((N + 127) / 128) * 128;
     I->Np = ((N + 127) / 128) * 128 + 128;
     const size_t Np = (size_t)I->Np;
     if ((st = dev_alloc(&I->J, Np * Np)) != MARS_OK)
@@ -257,9 +259,15 @@ static mars_status create_dense(const float *J, const float *h, int N, Instance 
         return st;
     launch_dense_fixpoint(*I, I->own_stream);
     MARS_HIP(hipGetLastError());
+    if ((st = dev_alloc(&I->Jlimb, (size_t)I->nlimb * I->Me * I->Ke)) != MARS_OK)
+        return st;
+    launch_dense_limbs(*I, I->own_stream);
+    MARS_HIP(hipGetLastError());
     if ((st = upload_h(I, h, I->Np)) != MARS_OK)
         return st;
     MARS_HIP(hipStreamSynchronize(I->own_stream));
+    MARS_HIP(hipFree(I->Jfix));
+    I->Jfix = nullptr;
     return MARS_OK;
 }
 
@@ -569,11 +577,14 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
                 break;
         }
     }
-    launch_dense_round(cur, ldm, N, R, spins, m_final, s);
-    launch_energy_from_spins(*I, spins, R, E, I->ws.partial.p, s);
+    if ((st = ensure(w.spad, dense_spin_operand_bytes(*I, R))) != MARS_OK)
+        return st;
+    int8_t *spad = (int8_t *)w.spad.p;
+    launch_dense_round(cur, ldm, N, R, I->Ke, spad, spins, m_final, s);
+    launch_dense_energy_i8(*I, spad, R, E, I->ws.partial.p, s);
     launch_argmin(E, T0, runstat, R, N, I->wsum, res_dev, best_dev, s);
     if (best_spins)
-        launch_gather_best(spins, best_dev, N, best_spins, s);
+        launch_gather_best(spad, I->Ke, best_dev, N, best_spins, s);
     MARS_HIP(hipGetLastError());
     return MARS_OK;
 }
@@ -600,10 +611,10 @@ static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint
     g.runstat = (int64_t *)w.runstat.p;
     if ((st = launch_graph_solve(*I, g, s)) != MARS_OK)
         return st;
-    launch_energy_from_spins(*I, spins, R, E, I->ws.partial.p, s);
+    launch_graph_energy(*I, spins, R, E, s);
     launch_argmin(E, T0, g.runstat, R, I->N, I->wsum, res_dev, best_dev, s);
     if (best_spins)
-        launch_gather_best(spins, best_dev, I->N, best_spins, s);
+        launch_gather_best(spins, I->N, best_dev, I->N, best_spins, s);
     MARS_HIP(hipGetLastError());
     return MARS_OK;
 }
@@ -624,7 +635,8 @@ static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, ui
     const size_t spin_bytes = (size_t)R * I->N;
     if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK)
         return st;
-    if (!spins) {
+    if (!spins && I->kind != KIND_DENSE) {
+        // lattice/sparse solves always write every run's spins (energy and best-run input)
         if ((st = ensure(w.spins, spin_bytes)) != MARS_OK)
             return st;
         spins = (int8_t *)w.spins.p;
@@ -634,7 +646,7 @@ static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, ui
             return st;
         E = (double *)w.energies.p;
     }
-    if ((st = ensure(w.partial, energy_partial_bytes(*I, R))) != MARS_OK)
+    if (I->kind == KIND_DENSE && (st = ensure(w.partial, dense_energy_partial_bytes(*I, R))) != MARS_OK)
         return st;
     mars_result *res_dev = (mars_result *)w.result.p;
     int32_t *best_dev = (int32_t *)((char *)w.result.p + sizeof(mars_result) + 16);
@@ -830,11 +842,17 @@ mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, dou
     Instance *I = reinterpret_cast<Instance *>(inst);
     std::lock_guard<std::mutex> lk(I->mu);
     MARS_HIP(hipSetDevice(I->device));
-    mars_status st = ensure(I->ws.partial, energy_partial_bytes(*I, R));
-    if (st != MARS_OK)
-        return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    launch_energy_from_spins(*I, spins, R, energies, I->ws.partial.p, s);
+    if (I->kind == KIND_DENSE) {
+        mars_status st;
+        if ((st = ensure(I->ws.partial, dense_energy_partial_bytes(*I, R))) != MARS_OK ||
+            (st = ensure(I->ws.spad, dense_spin_operand_bytes(*I, R))) != MARS_OK)
+            return st;
+        launch_pad_spins(*I, spins, R, (int8_t *)I->ws.spad.p, s);
+        launch_dense_energy_i8(*I, (const int8_t *)I->ws.spad.p, R, energies, I->ws.partial.p, s);
+    } else {
+        launch_graph_energy(*I, spins, R, energies, s);
+    }
     MARS_HIP(hipGetLastError());
     return MARS_OK;
 }
