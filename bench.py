@@ -22,6 +22,14 @@ if ROOT not in sys.path:
 METRIC = "spin-updates/s (runs×N×steps) at equal best-energy gap; p50/p99 solve latency"
 PEAK = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s
 
+# HBM bytes of one dense phase launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch, SK2000 workload), scaled by the counters' reading of a
+# plain 256 MiB copy.  Valid only for the kernel source they were taken on.
+TRAFFIC_RECORD = {"source": "paper_1907_05124_amd/csrc/dense_phase.h", "sha256_prefix": "da7ff34fb8baa29f",
+                  "workload": "sk2000", "fetch_kib": 55140.9, "write_kib": 16000.0,
+                  "fetch_scale": 2.0, "write_scale": 1.0,
+                  "summary": "profiles/k_dense_phase_f32_sk2000.md"}
+
 DESCRIPTION = {
     "sk2000": "SK N=2000 J~N(0,1/N) fp32, 4096 runs, T0~U[0.25,1.5]*sigma, 300 geometric levels to 0.01*sigma, "
               "2 phases",
@@ -30,6 +38,19 @@ DESCRIPTION = {
     "er20000": "Erdos-Renyi N=20000 avg degree 4 +-1 weights (J=-w), 8192 runs, 300 levels, fp32",
     "ea3d_L32": "3D +-J lattice 32^3 periodic, 2048 runs, 1000 levels, fp16 magnetisation storage",
 }
+
+
+def recorded_traffic(workload):
+    """Bytes per launch from the recorded counters, or None if the kernel changed since."""
+    import hashlib
+
+    rec = TRAFFIC_RECORD
+    if workload != rec["workload"]:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_prefix"]:
+            return None
+    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
 
 
 def log(*a):
@@ -169,7 +190,7 @@ def main():
         achieved = flops / per_launch_s / 1e12
         peak = PEAK["fp32_mfma"]
         roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4), "traffic": None,
+                    "frac": round(achieved / peak, 4), "traffic": recorded_traffic(args.workload),
                     "kernel": "k_dense_phase_f32", "launch_us": round(per_launch_s * 1e6, 3),
                     "flops_per_launch": flops}
 
