@@ -1,0 +1,197 @@
+// BF16 form of the dense update phase: couplings and magnetisations stored in
+// bfloat16, products on the bf16 matrix cores with fp32 accumulation, the
+// update (tanh, damping, per-run max change) in fp32, the new magnetisation
+// rounded to bf16 (device code; included by the library's dense unit).
+//
+// State layout: M^T [ldr x ldk] bf16, row = run, spins contiguous.  One phase
+// computes Phi^T[runs, P] = M^T[runs, :] * J[:, P] = M^T * (J[P, :])^T (J is
+// symmetric), so both operands are K-contiguous rows: run rows of M^T and
+// spin rows of J.  Ping-pong exactly as the fp32 form: spins k < p0 come from
+// the buffer being written this sweep, the rest from the previous one.
+//
+// Workgroup tile BM runs x BN spins, K in 64-element slabs through
+// double-buffered LDS (rows padded to 72 elements), WM x WN waves, each wave
+// (BM/WM) x (BN/WN) made of 32 x 32 blocks of the 32x32x16 bf16 MFMA.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mars {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
+
+constexpr int HBK = 64;        // slab depth (elements)
+constexpr int HLD = HBK + 8;   // padded LDS row (elements)
+
+__device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round to nearest even (finite inputs; magnetisations are in [-1, 1])
+__device__ inline unsigned short float_to_bf16(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
+    const unsigned short *__restrict__ J, int ldj, const unsigned short *__restrict__ Mold,
+    unsigned short *__restrict__ Mnew, int ldk, int R, int p0, int p1, int nrt, int nct, int kpad,
+    const float *__restrict__ invT, const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax)
+{
+    constexpr int NT = 64 * WM * WN;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int MB = TM / 32, NB = TN / 32;
+    constexpr int CA = BM * HBK / 8, CB = BN * HBK / 8;  // 16-byte chunks per slab
+    constexpr int LA = (CA + NT - 1) / NT, LB = (CB + NT - 1) / NT;
+    static_assert(MB >= 1 && NB >= 1, "tile shape");
+
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][BM][HLD];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN][HLD];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int li = lane & 31, kh = lane >> 5;
+
+    // tile order: the workgroups of one XCD share a band of runs (rows of M^T)
+    const int total = nrt * nct;
+    int t = blockIdx.x;
+    if ((total & 7) == 0)
+        t = (t & 7) * (total >> 3) + (t >> 3);
+    const int rt = t / nct, ct = t % nct;
+    const int r0 = rt * BM;
+    const int i0 = p0 + ct * BN;
+
+    floatx16 acc[MB][NB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                acc[a][b][v] = 0.0f;
+
+    ushortx8 ga[LA], gb[LB];
+    // A chunk: run row, 8 spins; spins below p0 from the new buffer, a chunk
+    // straddling p0 is blended element by element
+    auto load_a = [&](ushortx8 &dst, int c, int k0) {
+        const int row = c >> 3, kc = k0 + (c & 7) * 8;
+        const size_t off = (size_t)(r0 + row) * ldk + kc;
+        if (kc + 8 <= p0) {
+            dst = *reinterpret_cast<const ushortx8 *>(Mnew + off);
+        } else if (kc >= p0) {
+            dst = *reinterpret_cast<const ushortx8 *>(Mold + off);
+        } else {
+            const ushortx8 x = *reinterpret_cast<const ushortx8 *>(Mnew + off);
+            const ushortx8 y = *reinterpret_cast<const ushortx8 *>(Mold + off);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                dst[e] = (kc + e < p0) ? x[e] : y[e];
+        }
+    };
+#define H_LOAD(k0)                                                                                  \
+    _Pragma("unroll") for (int q = 0; q < LA; ++q)                                                  \
+    {                                                                                               \
+        const int c_ = tid + q * NT;                                                                \
+        if (c_ < CA)                                                                                \
+            load_a(ga[q], c_, (k0));                                                                \
+    }                                                                                               \
+    _Pragma("unroll") for (int q = 0; q < LB; ++q)                                                  \
+    {                                                                                               \
+        const int c_ = tid + q * NT;                                                                \
+        if (c_ < CB)                                                                                \
+            gb[q] = *reinterpret_cast<const ushortx8 *>(J + (size_t)(i0 + (c_ >> 3)) * ldj + (k0) + (c_ & 7) * 8); \
+    }
+#define H_STORE(buf)                                                                                \
+    _Pragma("unroll") for (int q = 0; q < LA; ++q)                                                  \
+    {                                                                                               \
+        const int c_ = tid + q * NT;                                                                \
+        if (c_ < CA)                                                                                \
+            *reinterpret_cast<ushortx8 *>(&As[(buf)][c_ >> 3][(c_ & 7) * 8]) = ga[q];               \
+    }                                                                                               \
+    _Pragma("unroll") for (int q = 0; q < LB; ++q)                                                  \
+    {                                                                                               \
+        const int c_ = tid + q * NT;                                                                \
+        if (c_ < CB)                                                                                \
+            *reinterpret_cast<ushortx8 *>(&Bs[(buf)][c_ >> 3][(c_ & 7) * 8]) = gb[q];               \
+    }
+
+    const int nk = kpad / HBK;
+    H_LOAD(0);
+    H_STORE(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) {
+            H_LOAD((kt + 1) * HBK);
+        }
+#pragma unroll
+        for (int ks = 0; ks < HBK / 16; ++ks) {
+            bf16x8 fa[MB], fb[NB];
+#pragma unroll
+            for (int a = 0; a < MB; ++a)
+                fa[a] = *reinterpret_cast<const bf16x8 *>(&As[cur][wm * TM + a * 32 + li][ks * 16 + kh * 8]);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                fb[b] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][wn * TN + b * 32 + li][ks * 16 + kh * 8]);
+#pragma unroll
+            for (int a = 0; a < MB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+        if (kt + 1 < nk) {
+            H_STORE(cur ^ 1);
+        }
+        __syncthreads();
+    }
+#undef H_LOAD
+#undef H_STORE
+
+    // epilogue: element (run = row, spin = column) of each 32 x 32 block; lane
+    // l holds spin column l%32, register v holds run row 8*(v/4) + 4*(l/32) + v%4
+    const bool damp = gamma != 1.0f;
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int run = r0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+            const bool rok = run < R;
+            const float it = rok ? invT[run] : -1.0f;
+            float dl = 0.0f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int spin = i0 + wn * TN + b * 32 + li;
+                if (rok && spin < p1) {
+                    const size_t off = (size_t)run * ldk + spin;
+                    const float old = bf16_to_float(Mold[off]);
+                    float nw = old;
+                    if (it >= 0.0f) {
+                        float phi = acc[a][b][v];
+                        if (hhalf)
+                            phi += hhalf[spin];
+                        const float th = tanhf(phi * it);
+                        nw = damp ? (1.0f - gamma) * old + gamma * th : th;
+                    }
+                    const unsigned short nb16 = float_to_bf16(nw);
+                    Mnew[off] = nb16;
+                    dl = fmaxf(dl, fabsf(bf16_to_float(nb16) - old));
+                }
+            }
+            if (dmax) {
+                // per-run maximum over the 32 spin lanes of this half-wave
+#pragma unroll
+                for (int m = 16; m >= 1; m >>= 1)
+                    dl = fmaxf(dl, __shfl_xor(dl, m));
+                if (li == 0 && rok)
+                    atomicMax(&dmax[run], __float_as_uint(dl));
+            }
+        }
+    }
+}
+
+}  // namespace mars

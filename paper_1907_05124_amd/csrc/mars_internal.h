@@ -48,7 +48,7 @@ struct Instance {
     // dense
     int Np = 0;             // padded dimension of J and of the state rows
     float *J = nullptr;     // [Np x Np] zero padded
-    uint16_t *Jbf = nullptr;  // [Np x Np] bf16 copy (created on first bf16 solve)
+    unsigned short *Jbf = nullptr;  // [Np x Np] bf16 copy (created on the first bf16 solve)
     int64_t *Jfix = nullptr;  // [N x N] fixed-point couplings (create-time only)
     int8_t *Jlimb = nullptr;  // [nlimb x Me x Ke] balanced base-256 digits of Jfix
     int nlimb = 0;
@@ -117,6 +117,15 @@ void launch_dense_advance_init(int R, const float *table, const int32_t *nlev, f
 void launch_dense_advance(int R, const float *table, int ldt, const int32_t *nlev, int max_sweeps, double d_min,
                           float *invT_cur, int32_t *state, int64_t *runstat, uint32_t *dmax, uint32_t *active,
                           hipStream_t s);
+
+// dense, bf16 form (k_dense_bf16.hip)
+mars_status ensure_bf16_couplings(Instance &I, hipStream_t s);
+int bf16_state_rows(int R);
+void launch_bf16_init_state(uint64_t seed, int N, int R, int ldk, const float *m0, unsigned short *MT, hipStream_t s);
+void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R,
+                             int p0, int p1, const float *invT, float gamma, uint32_t *dmax, hipStream_t s);
+void launch_bf16_round(const unsigned short *MT, int ldk, int N, int R, int Ke, int8_t *spad, int8_t *spins,
+                       float *m_final, hipStream_t s);
 
 // graph (lattice and csr): the whole anneal of a block of runs in LDS
 struct GraphSolve {

@@ -497,21 +497,25 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
                                const double *T0in, float *m_final, int8_t *spins, double *E, int8_t *best_spins,
                                mars_result *res_dev, int32_t *best_dev, hipStream_t s)
 {
-    if (sc.precision != MARS_FP32)
-        return set_error(MARS_E_UNSUPPORTED, "dense instances currently support MARS_FP32");
+    if (sc.precision != MARS_FP32 && sc.precision != MARS_BF16)
+        return set_error(MARS_E_UNSUPPORTED, "dense instances support MARS_FP32 and MARS_BF16");
+    const bool bf16 = sc.precision == MARS_BF16;
     Workspace &w = I->ws;
     const int N = I->N;
-    const int ldm = ((R + 127) / 128) * 128;
-    const size_t mbytes = sizeof(float) * (size_t)I->Np * ldm;
     mars_status st;
+    if (bf16 && (st = ensure_bf16_couplings(*I, s)) != MARS_OK)
+        return st;
+    // state: fp32 [Np x ldm] spin-major, or bf16 [ldr x Np] run-major
+    const int ldm = ((R + 127) / 128) * 128;
+    const int ldr = bf16_state_rows(R);
+    const size_t mbytes = bf16 ? sizeof(unsigned short) * (size_t)ldr * I->Np : sizeof(float) * (size_t)I->Np * ldm;
     if ((st = ensure(w.Ma, mbytes)) || (st = ensure(w.Mb, mbytes)) || (st = ensure(w.T0, sizeof(double) * R)) ||
         (st = ensure(w.nlev, sizeof(int32_t) * R)) || (st = ensure(w.runstat, sizeof(int64_t) * 4 * R)) ||
-        (st = ensure(w.dmax, sizeof(uint32_t) * ldm)) || (st = ensure(w.runstate, sizeof(int32_t) * 4 * ldm)) ||
+        (st = ensure(w.dmax, sizeof(uint32_t) * ldr)) || (st = ensure(w.runstate, sizeof(int32_t) * 4 * ldr)) ||
         (st = ensure(w.flag, 64)))
         return st;
-    float *Ma = (float *)w.Ma.p, *Mb = (float *)w.Mb.p;
-    launch_fill_u32((uint32_t *)Ma, 0u, mbytes / 4, s);
-    launch_fill_u32((uint32_t *)Mb, 0u, mbytes / 4, s);
+    launch_fill_u32((uint32_t *)w.Ma.p, 0u, mbytes / 4, s);
+    launch_fill_u32((uint32_t *)w.Mb.p, 0u, mbytes / 4, s);
     double *T0 = (double *)w.T0.p;
     launch_init_T0(seed, R, sc.T_lo, sc.T_hi, T0in, T0, s);
     double Tmax = sc.T_hi;
@@ -526,33 +530,46 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
     int kmax = 0;
     if ((st = max_levels(sc, Tmax, &kmax)) != MARS_OK)
         return st;
-    if ((st = ensure(w.invT, sizeof(float) * (size_t)std::max(kmax, 1) * ldm)) != MARS_OK)
+    if ((st = ensure(w.invT, sizeof(float) * (size_t)std::max(kmax, 1) * ldr)) != MARS_OK)
         return st;
+    // one table row per level; ldr >= ldm, so the same stride serves both forms
+    const int ldt = ldr;
     float *table = (float *)w.invT.p;
     int32_t *nlev = (int32_t *)w.nlev.p;
-    launch_level_table(sc, R, T0, kmax, ldm, table, nullptr, nlev, s);
-    launch_dense_init_state(seed, N, R, ldm, m0, Ma, s);
+    launch_level_table(sc, R, T0, kmax, ldt, table, nullptr, nlev, s);
+    if (bf16)
+        launch_bf16_init_state(seed, N, R, I->Np, m0, (unsigned short *)w.Ma.p, s);
+    else
+        launch_dense_init_state(seed, N, R, ldm, m0, (float *)w.Ma.p, s);
 
     const int B = sc.update == MARS_JACOBI ? 1 : std::min(sc.phases, N);
     std::vector<int> pb((size_t)B + 1);
     for (int b = 0; b <= B; ++b)
         pb[b] = (int)((long long)b * N / B);
     const float gamma = (float)sc.damping;
-    float *cur = Ma, *nxt = Mb;
+    void *cur = w.Ma.p, *nxt = w.Mb.p;
+    auto sweep = [&](const float *invT, uint32_t *dmax) {
+        for (int b = 0; b < B; ++b) {
+            if (pb[b + 1] <= pb[b])
+                continue;
+            if (bf16)
+                launch_dense_phase_bf16(*I, (const unsigned short *)cur, (unsigned short *)nxt, I->Np, R, pb[b],
+                                        pb[b + 1], invT, gamma, dmax, s);
+            else
+                launch_dense_phase_f32(*I, (const float *)cur, (float *)nxt, ldm, R, pb[b], pb[b + 1], invT, gamma,
+                                       dmax, s);
+        }
+        std::swap(cur, nxt);
+    };
     int64_t *runstat = (int64_t *)w.runstat.p;
     if (sc.max_sweeps == 1) {
-        for (int k = 0; k < kmax; ++k) {
-            for (int b = 0; b < B; ++b)
-                if (pb[b + 1] > pb[b])
-                    launch_dense_phase_f32(*I, cur, nxt, ldm, R, pb[b], pb[b + 1], table + (size_t)k * ldm, gamma,
-                                           nullptr, s);
-            std::swap(cur, nxt);
-        }
+        for (int k = 0; k < kmax; ++k)
+            sweep(table + (size_t)k * ldt, nullptr);
         launch_dense_runstat(R, nlev, runstat, s);
     } else {
         // several sweeps per level: per-run level state advanced on the device
-        float *invT_cur = (float *)w.runstate.p;  // [ldm] floats followed by [ldm x 2] ints
-        int32_t *state = (int32_t *)(invT_cur + ldm);
+        float *invT_cur = (float *)w.runstate.p;  // [ldr] floats followed by [ldr x 2] ints
+        int32_t *state = (int32_t *)(invT_cur + ldr);
         uint32_t *dmax = (uint32_t *)w.dmax.p;
         uint32_t *active = (uint32_t *)w.flag.p;
         launch_dense_advance_init(R, table, nlev, invT_cur, state, runstat, dmax, s);
@@ -561,12 +578,9 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
         const int chunk = 8;
         while (done_sweeps < cap) {
             for (int c = 0; c < chunk; ++c) {
-                for (int b = 0; b < B; ++b)
-                    if (pb[b + 1] > pb[b])
-                        launch_dense_phase_f32(*I, cur, nxt, ldm, R, pb[b], pb[b + 1], invT_cur, gamma, dmax, s);
-                std::swap(cur, nxt);
+                sweep(invT_cur, dmax);
                 launch_fill_u32(active, 0u, 1, s);
-                launch_dense_advance(R, table, ldm, nlev, sc.max_sweeps, sc.d_min, invT_cur, state, runstat, dmax,
+                launch_dense_advance(R, table, ldt, nlev, sc.max_sweeps, sc.d_min, invT_cur, state, runstat, dmax,
                                      active, s);
                 ++done_sweeps;
             }
@@ -580,7 +594,10 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
     if ((st = ensure(w.spad, dense_spin_operand_bytes(*I, R))) != MARS_OK)
         return st;
     int8_t *spad = (int8_t *)w.spad.p;
-    launch_dense_round(cur, ldm, N, R, I->Ke, spad, spins, m_final, s);
+    if (bf16)
+        launch_bf16_round((const unsigned short *)cur, I->Np, N, R, I->Ke, spad, spins, m_final, s);
+    else
+        launch_dense_round((const float *)cur, ldm, N, R, I->Ke, spad, spins, m_final, s);
     launch_dense_energy_i8(*I, spad, R, E, I->ws.partial.p, s);
     launch_argmin(E, T0, runstat, R, N, I->wsum, res_dev, best_dev, s);
     if (best_spins)
