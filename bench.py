@@ -32,6 +32,9 @@ TRAFFIC_RECORD = {
     "fp32": {"source": "paper_1907_05124_amd/csrc/dense_phase.h", "sha256_prefix": "da7ff34fb8baa29f",
              "workload": "sk2000", "fetch_kib": 55140.9, "write_kib": 16000.0,
              "fetch_scale": 2.0, "write_scale": 1.0, "summary": "profiles/k_dense_phase_f32_sk2000.md"},
+    "bf16": {"source": "paper_1907_05124_amd/csrc/dense_phase_bf16.h", "sha256_prefix": "7b0c9dadb3c653c6",
+             "workload": "sk2000", "fetch_kib": 26786.0, "write_kib": 8064.0,
+             "fetch_scale": 2.0, "write_scale": 1.0, "summary": "profiles/k_dense_phase_bf16_sk2000.md"},
 }
 
 DESCRIPTION = {
