@@ -44,6 +44,9 @@ DESCRIPTION = {
     "er800": "Erdos-Renyi N=800 p=0.06 +-1 weights (J=-w), 8192 runs, 300 levels, greedy-colour phases, fp32",
     "er20000": "Erdos-Renyi N=20000 avg degree 4 +-1 weights (J=-w), 8192 runs, 300 levels, fp32",
     "ea3d_L32": "3D +-J lattice 32^3 periodic, 2048 runs, 1000 levels, fp16 magnetisation storage",
+    "served": "served mixed stream: Poisson arrivals, N log-uniform in [100,10000], half dense SK (bf16 form), "
+              "half ER degree-4 +-1 (fp32), 256-4096 runs each, 300 levels; admission by HBM footprint, "
+              "concurrent solves on 4 streams",
 }
 
 
@@ -112,6 +115,47 @@ def copy_calibration():
                       "GB/s": 2 * n * 4 / ms / 1e6}), flush=True)
 
 
+def served(args):
+    """Served mixed stream: a capacity pass (all requests at t = 0), then a
+    Poisson pass at 70 % of that capacity; latency is arrival to result."""
+    import numpy as np
+    import torch
+
+    from paper_1907_05124_amd import serve as S
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    server = S.MarsServer(max_active=8, n_streams=4)
+
+    def make(rate):
+        reqs = S.mixed_stream(args.requests, rate, seed=args.seed)
+        for r in reqs:  # synthetic inputs are generated before the clock starts
+            r.instance = r.materialize()
+        return reqs
+
+    warm = S.mixed_stream(4, 1e9, seed=args.seed + 7, n_hi=500)
+    server.run(warm)
+    cap_reqs = make(1e9)
+    log("capacity pass: %d requests" % len(cap_reqs))
+    _, cap = server.run(cap_reqs)
+    rate = 0.7 * cap["requests"] / cap["makespan_s"]
+    log("capacity", cap, "-> offered rate %.2f req/s" % rate)
+    load_reqs = make(rate)
+    _, st = server.run(load_reqs)
+    log("load pass", st)
+    line = {
+        "metric": METRIC, "value": st["spin_updates_per_s"], "unit": "spin-updates/s", "n_gpus": 1,
+        "steps": st["requests"], "warmup": len(warm), "ms_per_step": st["makespan_s"] * 1e3 / max(1, st["requests"]),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (dense) / f32 (sparse)",
+        "data": "synthetic",
+        "config": {"workload": "served", "description": DESCRIPTION["served"], "requests": st["requests"],
+                   "offered_rate_per_s": rate, "parallelism": "single GPU, concurrent streams"},
+        "latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"]},
+        "capacity": cap, "load": st, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,11 +166,17 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16", "fp16"],
                     help="override the workload's arithmetic form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=200, help="served workload: number of requests")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (to scale rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
+    if args.workload == "served":
+        if args.gpus != 1:
+            print("bench.py measures one GPU.", file=sys.stderr)
+            sys.exit(2)
+        return served(args)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (runs would shard by index "
               "across GPUs; see the design notes).  Run with --gpus 1.", file=sys.stderr)

@@ -178,6 +178,18 @@ mars_status mars_solve_ex(mars_instance *inst, int32_t runs, const mars_schedule
                           const void *m0, const double *T0, double *T0_used, void *m_final, int8_t *spins,
                           double *energies, int8_t *best_spins, mars_result *res, void *stream);
 
+/* Asynchronous solve for serving many instances concurrently: as
+ * mars_solve_ex, but the summary is copied into res_pinned (HOST memory
+ * allocated pinned, e.g. hipHostMalloc) by an asynchronous copy on `stream`;
+ * the call returns after enqueueing and every output, including *res_pinned,
+ * is valid once the stream has passed the enqueued work.  res_pinned may be
+ * NULL.  Solves and energy calls on one instance may use different streams:
+ * each waits on the stream for the instance's previous work (its workspace
+ * is shared).  Errors as mars_solve. */
+mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
+                             const void *m0, const double *T0, void *m_final, int8_t *spins, double *energies,
+                             int8_t *best_spins, mars_result *res_pinned, void *stream);
+
 /* Exact energies (eq. (2)) of R spin vectors.  spins: DEVICE int8 [R x N]
  * (values +-1); energies: DEVICE double [R].  stream as in mars_solve_ex;
  * the call returns after enqueueing.  Errors: MARS_E_ARG, MARS_E_DEVICE. */

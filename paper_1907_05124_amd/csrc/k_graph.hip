@@ -13,6 +13,7 @@
 // so they are updated in place; the next phase sees the new values, which is
 // sequential dynamics in colour order.  The synchronous variant keeps a
 // second copy and swaps after each sweep.
+#include <algorithm>
 #include <cmath>
 
 #include "common_device.h"
@@ -41,8 +42,18 @@ struct StoreOps<_Float16> {
     __device__ static inline _Float16 st(float v) { return (_Float16)v; }
 };
 
+// tanh: the library routine in fp64; in fp32 the identity
+// tanh(a) = 1 - 2 / (exp(2a) + 1) on |a| with the hardware exp2 and reciprocal
+// (absolute error ~1e-7, far below the fp32 form's 1e-5 bar and the fp16
+// storage step), sign restored afterwards so that tanh stays exactly odd.
 __device__ inline double mf_tanh(double x) { return tanh(x); }
-__device__ inline float mf_tanh(float x) { return tanhf(x); }
+__device__ inline float mf_tanh(float x)
+{
+    const float a = fabsf(x);
+    const float e = __builtin_amdgcn_exp2f(a * 2.8853900817779268f);  // exp(2a) = 2^(2a / ln 2)
+    const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+    return copysignf(t, x);
+}
 // Phi / T: a true division in fp64 (the reference arithmetic), a multiply by
 // the rounded inverse in fp32.
 __device__ inline double scale_T(double phi, double T, double invT) { return phi / T; }
@@ -87,7 +98,7 @@ __device__ inline float hhalf_of<float>(const GraphArgs &a, int i) { return a.hh
 
 // IS_LAT: lattice (neighbours from coordinates) or CSR.  JAC: synchronous
 // update.  TRACKD: several sweeps per level, ended by d < d_min.
-template <bool IS_LAT, typename S, bool JAC, bool TRACKD>
+template <bool IS_LAT, typename S, bool JAC, bool TRACKD, bool HAS_H>
 __global__ __launch_bounds__(1024) void k_graph_solve(GraphArgs a)
 {
     typedef typename StoreOps<S>::C C;
@@ -181,7 +192,8 @@ __global__ __launch_bounds__(1024) void k_graph_solve(GraphArgs a)
                                 phi += (b & 16) ? -t4 : t4;
                                 phi += (b & 32) ? -t5 : t5;
                             }
-                            phi += hhalf_of<C>(a, v);
+                            if (HAS_H)
+                                phi += hhalf_of<C>(a, v);
                             const C th = mf_tanh(scale_T(phi, Tcur, invT));
                             nw = damp ? ((C)1 - g) * old + g * th : th;
                             const C dd = nw > old ? nw - old : old - nw;
@@ -215,7 +227,8 @@ __global__ __launch_bounds__(1024) void k_graph_solve(GraphArgs a)
                             const C w = (C)(int8_t)(cv & 0xff);
                             phi += w * StoreOps<S>::ld(m[u * rpw + q]);
                         }
-                        phi += hhalf_of<C>(a, v);
+                        if (HAS_H)
+                            phi += hhalf_of<C>(a, v);
                         const C th = mf_tanh(scale_T(phi, Tcur, invT));
                         nw = damp ? ((C)1 - g) * old + g * th : th;
                         const C dd = nw > old ? nw - old : old - nw;
@@ -295,15 +308,20 @@ __global__ __launch_bounds__(1024) void k_graph_solve(GraphArgs a)
     }
 }
 
+template <bool IS_LAT, typename S, bool HAS_H>
+static void (*pick(bool jac, bool trackd))(GraphArgs)
+{
+    if (jac)
+        return trackd ? k_graph_solve<IS_LAT, S, true, true, HAS_H> : k_graph_solve<IS_LAT, S, true, false, HAS_H>;
+    return trackd ? k_graph_solve<IS_LAT, S, false, true, HAS_H> : k_graph_solve<IS_LAT, S, false, false, HAS_H>;
+}
+
 template <bool IS_LAT, typename S>
 static hipError_t launch_one(const GraphArgs &a, bool jac, bool trackd, dim3 grid, dim3 block, size_t lds,
                              hipStream_t s)
 {
-    void (*fn)(GraphArgs);
-    if (jac)
-        fn = trackd ? k_graph_solve<IS_LAT, S, true, true> : k_graph_solve<IS_LAT, S, true, false>;
-    else
-        fn = trackd ? k_graph_solve<IS_LAT, S, false, true> : k_graph_solve<IS_LAT, S, false, false>;
+    const bool has_h = a.hhalf32 != nullptr;
+    void (*fn)(GraphArgs) = has_h ? pick<IS_LAT, S, true>(jac, trackd) : pick<IS_LAT, S, false>(jac, trackd);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -331,22 +349,32 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     const size_t lds_cap = 160 * 1024 - 1024;
     if (per_run + 64 > lds_cap)
         return set_error(MARS_E_UNSUPPORTED, "the state of one run does not fit in LDS (N too large for this kernel)");
-    // runs per workgroup: fill LDS up to 64 KB (two or more workgroups per CU)
-    // but keep at least ~512 workgroups when there are enough runs
+    // runs per workgroup: as many as fit the LDS budget while at least one
+    // workgroup per CU (256) remains; more runs per workgroup give each phase
+    // more independent (spin, run) items per barrier
     int rpw = 1;
-    while (rpw < 64 && (size_t)(2 * rpw) * per_run + 256 <= 65536 && 2 * rpw * 512 <= g.R)
+    while (rpw < 64 && (size_t)(2 * rpw) * per_run + 256 <= lds_cap && 2 * rpw * 256 <= g.R)
         rpw *= 2;
-    int Tq;
-    if (rpw == 1 && N >= 4096)
-        Tq = 1024;
-    else
-        Tq = 256 / rpw;
+    // threads per run: at most 1024 per workgroup and no more than the
+    // largest phase has spins (lattice: N/2; sparse: the largest colour class)
+    int Tq = 1024 / rpw;
+    int widest = N;
+    if (!jac) {
+        if (I.kind == KIND_LATTICE) {
+            widest = (N + 1) / 2;
+        } else {
+            widest = 1;
+            for (size_t c = 0; c + 1 < I.h_phase_ptr.size(); ++c)
+                widest = std::max(widest, I.h_phase_ptr[c + 1] - I.h_phase_ptr[c]);
+        }
+    }
+    Tq = std::max(1, std::min(Tq, (widest + 63) / 64 * 64));
     if (I.kind == KIND_LATTICE) {
         const int H = I.L[0] / 2;
         if (Tq < H) {
-            while (rpw > 1 && 256 / rpw < H)
+            while (rpw > 1 && 1024 / rpw < H)
                 rpw /= 2;
-            Tq = 256 / rpw;
+            Tq = 1024 / rpw;
             if (Tq < H)
                 Tq = H;
         }

@@ -71,6 +71,10 @@ struct Instance {
     uint8_t *bondbits = nullptr;  // [N]: bit 2a set if J(v, v+e_a) < 0, bit 2a+1 if J(v, v-e_a) < 0
     // runtime
     hipStream_t own_stream = nullptr;
+    // the instance's workspace is reused by every solve: a solve on another
+    // stream first waits for the previous one (recorded in done_event)
+    hipEvent_t done_event = nullptr;
+    bool done_recorded = false;
     Workspace ws;
     std::mutex mu;
 };

@@ -80,6 +80,10 @@ static void destroy_instance(Instance *I)
     (void)hipSetDevice(I->device);
     if (I->own_stream)
         (void)hipStreamSynchronize(I->own_stream);
+    if (I->done_event) {
+        (void)hipEventSynchronize(I->done_event);
+        (void)hipEventDestroy(I->done_event);
+    }
     void *ptrs[] = {I->J, I->Jbf, I->Jfix, I->Jlimb, I->hhalf, I->hhalf64, I->hfix, I->rowptr,
                     I->colval, I->phase_ptr, I->phase_vert, I->bondbits};
     for (void *p : ptrs)
@@ -159,6 +163,9 @@ static mars_status start_instance(Instance *I)
     e = hipStreamCreateWithFlags(&I->own_stream, hipStreamNonBlocking);
     if (e != hipSuccess)
         return hip_error(e, "hipStreamCreate");
+    e = hipEventCreateWithFlags(&I->done_event, hipEventDisableTiming);
+    if (e != hipSuccess)
+        return hip_error(e, "hipEventCreate");
     return MARS_OK;
 }
 
@@ -201,9 +208,11 @@ static mars_status upload_h(Instance *I, const float *h, int padN)
         return st;
     if ((st = dev_alloc(&I->hfix, (size_t)N)) != MARS_OK)
         return st;
-    MARS_HIP(hipMemcpy(I->hhalf, hh.data(), sizeof(float) * padN, hipMemcpyHostToDevice));
-    MARS_HIP(hipMemcpy(I->hhalf64, hh64.data(), sizeof(double) * N, hipMemcpyHostToDevice));
-    MARS_HIP(hipMemcpy(I->hfix, hf.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice));
+    MARS_HIP(hipMemcpyAsync(I->hhalf, hh.data(), sizeof(float) * padN, hipMemcpyHostToDevice, I->own_stream));
+    MARS_HIP(hipMemcpyAsync(I->hhalf64, hh64.data(), sizeof(double) * N, hipMemcpyHostToDevice, I->own_stream));
+    MARS_HIP(hipMemcpyAsync(I->hfix, hf.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice, I->own_stream));
+    // the host vectors die on return: wait for the copies
+    MARS_HIP(hipStreamSynchronize(I->own_stream));
     return MARS_OK;
 }
 
@@ -252,9 +261,9 @@ static mars_status create_dense(const float *J, const float *h, int N, Instance 
     const size_t Np = (size_t)I->Np;
     if ((st = dev_alloc(&I->J, Np * Np)) != MARS_OK)
         return st;
-    MARS_HIP(hipMemset(I->J, 0, sizeof(float) * Np * Np));
-    MARS_HIP(hipMemcpy2D(I->J, sizeof(float) * Np, J, sizeof(float) * N, sizeof(float) * N, N,
-                         hipMemcpyHostToDevice));
+    MARS_HIP(hipMemsetAsync(I->J, 0, sizeof(float) * Np * Np, I->own_stream));
+    MARS_HIP(hipMemcpy2DAsync(I->J, sizeof(float) * Np, J, sizeof(float) * N, sizeof(float) * N, N,
+                              hipMemcpyHostToDevice, I->own_stream));
     if ((st = dev_alloc(&I->Jfix, (size_t)N * N)) != MARS_OK)
         return st;
     launch_dense_fixpoint(*I, I->own_stream);
@@ -364,10 +373,12 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
         return st;
     if ((st = dev_alloc(&I->phase_vert, (size_t)N)) != MARS_OK)
         return st;
-    MARS_HIP(hipMemcpy(I->rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice));
-    MARS_HIP(hipMemcpy(I->colval, cv.data(), sizeof(uint32_t) * cv.size(), hipMemcpyHostToDevice));
-    MARS_HIP(hipMemcpy(I->phase_ptr, pptr.data(), sizeof(int32_t) * pptr.size(), hipMemcpyHostToDevice));
-    MARS_HIP(hipMemcpy(I->phase_vert, pvert.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice));
+    hipStream_t s = I->own_stream;
+    MARS_HIP(hipMemcpyAsync(I->rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s));
+    MARS_HIP(hipMemcpyAsync(I->colval, cv.data(), sizeof(uint32_t) * cv.size(), hipMemcpyHostToDevice, s));
+    MARS_HIP(hipMemcpyAsync(I->phase_ptr, pptr.data(), sizeof(int32_t) * pptr.size(), hipMemcpyHostToDevice, s));
+    MARS_HIP(hipMemcpyAsync(I->phase_vert, pvert.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
+    MARS_HIP(hipStreamSynchronize(s));
     return upload_h(I, h, N);
 }
 
@@ -427,7 +438,8 @@ static mars_status create_lattice(int dim, const int32_t *L, const int8_t *bond,
     }
     if ((st = dev_alloc(&I->bondbits, (size_t)N)) != MARS_OK)
         return st;
-    MARS_HIP(hipMemcpy(I->bondbits, bits.data(), (size_t)N, hipMemcpyHostToDevice));
+    MARS_HIP(hipMemcpyAsync(I->bondbits, bits.data(), (size_t)N, hipMemcpyHostToDevice, I->own_stream));
+    MARS_HIP(hipStreamSynchronize(I->own_stream));
     return upload_h(I, h, (int)N);
 }
 
@@ -636,6 +648,22 @@ static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint
     return MARS_OK;
 }
 
+// Stream ordering of the shared workspace: wait for the instance's previous
+// work, then (after enqueueing) mark the new end of its work.
+static mars_status order_begin(Instance *I, hipStream_t s)
+{
+    if (I->done_recorded)
+        MARS_HIP(hipStreamWaitEvent(s, I->done_event, 0));
+    return MARS_OK;
+}
+
+static mars_status order_end(Instance *I, hipStream_t s)
+{
+    MARS_HIP(hipEventRecord(I->done_event, s));
+    I->done_recorded = true;
+    return MARS_OK;
+}
+
 static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, uint64_t seed, const void *m0,
                               const double *T0, void *m_final, int8_t *spins, double *E, int8_t *best_spins,
                               mars_result *res, hipStream_t s)
@@ -648,6 +676,8 @@ static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, ui
     if (st != MARS_OK)
         return st;
     MARS_HIP(hipSetDevice(I->device));
+    if ((st = order_begin(I, s)) != MARS_OK)
+        return st;
     Workspace &w = I->ws;
     const size_t spin_bytes = (size_t)R * I->N;
     if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK)
@@ -673,6 +703,8 @@ static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, ui
     else
         st = solve_graph(I, R, *sched, seed, m0, T0, m_final, spins, E, best_spins, res_dev, best_dev, s);
     if (st != MARS_OK)
+        return st;
+    if ((st = order_end(I, s)) != MARS_OK)
         return st;
     if (res) {
         mars_result tmp;
@@ -806,6 +838,22 @@ mars_status mars_solve_ex(mars_instance *inst, int32_t runs, const mars_schedule
     return MARS_OK;
 }
 
+mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
+                             const void *m0, const double *T0, void *m_final, int8_t *spins, double *energies,
+                             int8_t *best_spins, mars_result *res_pinned, void *stream)
+{
+    if (!inst)
+        return set_error(MARS_E_ARG, "instance is NULL");
+    Instance *I = reinterpret_cast<Instance *>(inst);
+    std::lock_guard<std::mutex> lk(I->mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    mars_status st = solve_impl(I, runs, sched, seed, m0, T0, m_final, spins, energies, best_spins, nullptr, s);
+    if (st != MARS_OK || !res_pinned)
+        return st;
+    MARS_HIP(hipMemcpyAsync(res_pinned, I->ws.result.p, sizeof(mars_result), hipMemcpyDeviceToHost, s));
+    return order_end(I, s);
+}
+
 mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
                        int8_t *best_spins, double *energies, mars_result *res)
 {
@@ -860,6 +908,11 @@ mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, dou
     std::lock_guard<std::mutex> lk(I->mu);
     MARS_HIP(hipSetDevice(I->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    {
+        mars_status st0 = order_begin(I, s);
+        if (st0 != MARS_OK)
+            return st0;
+    }
     if (I->kind == KIND_DENSE) {
         mars_status st;
         if ((st = ensure(I->ws.partial, dense_energy_partial_bytes(*I, R))) != MARS_OK ||
@@ -871,7 +924,7 @@ mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, dou
         launch_graph_energy(*I, spins, R, energies, s);
     }
     MARS_HIP(hipGetLastError());
-    return MARS_OK;
+    return order_end(I, s);
 }
 
 const char *mars_status_str(mars_status s)

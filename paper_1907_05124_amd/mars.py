@@ -51,7 +51,7 @@ class Result(C.Structure):
 
 
 EXPORTS = ["mars_create", "mars_create_csr", "mars_create_lattice", "mars_destroy", "mars_describe", "mars_solve",
-           "mars_solve_ex", "mars_energy", "mars_status_str", "mars_last_error"]
+           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_status_str", "mars_last_error"]
 
 _lib = None
 _lock = threading.Lock()
@@ -76,13 +76,14 @@ def load(path: str = LIB_PATH):
         L.mars_solve.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, C.POINTER(Result)]
         L.mars_solve_ex.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp,
                                     C.POINTER(Result), vp]
+        L.mars_solve_async.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mars_energy.argtypes = [vp, vp, i32, vp, vp]
         L.mars_status_str.argtypes = [C.c_int]
         L.mars_status_str.restype = C.c_char_p
         L.mars_last_error.argtypes = []
         L.mars_last_error.restype = C.c_char_p
         for f in ("mars_create", "mars_create_csr", "mars_create_lattice", "mars_describe", "mars_solve",
-                  "mars_solve_ex", "mars_energy"):
+                  "mars_solve_ex", "mars_solve_async", "mars_energy"):
             getattr(L, f).restype = C.c_int
         _lib = L
         return L
@@ -232,6 +233,34 @@ class Instance:
         if sync:
             out["result"] = res.as_dict()
         return out
+
+    def solve_async(self, runs: int, schedule, seed: int, result_buf, *, stream, want_energies=False,
+                    want_best=True, want_spins=False) -> dict:
+        """Enqueue a solve on `stream`; `result_buf` is a pinned uint8 tensor of
+        at least sizeof(Result) bytes that receives the summary asynchronously.
+        Returns the device output tensors (valid once the stream has passed)."""
+        import torch
+
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = {}
+        if want_energies:
+            out["energies"] = torch.empty(runs, dtype=torch.float64, device=dev)
+        if want_best:
+            out["best_spins"] = torch.empty(self.N, dtype=torch.int8, device=dev)
+        if want_spins:
+            out["spins"] = torch.empty((runs, self.N), dtype=torch.int8, device=dev)
+        s = make_schedule(schedule)
+        _check(load().mars_solve_async(self._h, int(runs), C.byref(s), seed & (2**64 - 1), None, None, None,
+                                       _ptr(out.get("spins")), _ptr(out.get("energies")),
+                                       _ptr(out.get("best_spins")), result_buf.data_ptr(),
+                                       C.c_void_p(stream.cuda_stream)))
+        return out
+
+    @staticmethod
+    def read_result(result_buf) -> dict:
+        """Decode a pinned result buffer filled by solve_async (after the stream passed it)."""
+        raw = bytes(result_buf.cpu().numpy()[: C.sizeof(Result)])
+        return Result.from_buffer_copy(raw).as_dict()
 
     def energy(self, spins):
         """Exact energies of device spins [R, N] int8 -> float64 [R] (current stream)."""

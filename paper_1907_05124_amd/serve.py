@@ -1,0 +1,299 @@
+"""Serving loop: continuous batching of Ising solve requests on one GPU.
+
+Requests (an instance, a number of runs, a schedule, a seed and an arrival
+time) are admitted as soon as they have arrived and both an active slot and
+enough HBM are free; each admitted request keeps its couplings and run state
+resident on the GPU while its solve runs on one of a pool of streams, so the
+work of different requests overlaps on the device.  Completed requests free
+their slot and memory; their device buffers are released when the GPU is idle
+or when the memory is needed (releasing device memory synchronises the
+device).
+
+Every solve is independent and deterministic (counter-based draws, fixed
+reduction orders), so a request's result is the same whether it runs alone
+or in the mix; ``tests/test_gpu_serve.py`` checks that bit for bit.
+
+The scheduling policy (``Scheduler``) is separate from the GPU executor so
+that it can be exercised without a GPU.
+"""
+from __future__ import annotations
+
+import heapq
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs as I
+
+# ---------------------------------------------------------------------------
+# requests and footprints
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class InstanceSpec:
+    """A synthetic instance described by kind, size and seed; materialised on
+    admission (dense N = 10^4 couplings are 400 MB of host memory)."""
+
+    kind: str  # "sk" | "er"
+    N: int
+    seed: int
+    avg_degree: float = 4.0
+
+    @property
+    def nnz(self) -> int:
+        return int(self.avg_degree * self.N) if self.kind == "er" else self.N * self.N
+
+    def materialize(self):
+        if self.kind == "sk":
+            return I.sk_instance(self.N, self.seed)
+        return I.er_instance(self.N, self.seed, avg_degree=min(self.avg_degree, self.N - 1.0), weights="pm1")
+
+
+@dataclass
+class Request:
+    rid: int
+    instance: object  # an inputs.*Instance or an InstanceSpec
+    runs: int
+    schedule: I.Schedule
+    seed: int
+    arrival: float = 0.0  # seconds after the start of the stream
+
+    @property
+    def N(self) -> int:
+        return self.instance.N
+
+    @property
+    def dense(self) -> bool:
+        if isinstance(self.instance, InstanceSpec):
+            return self.instance.kind == "sk"
+        return isinstance(self.instance, I.DenseInstance)
+
+    def materialize(self):
+        if isinstance(self.instance, InstanceSpec):
+            return self.instance.materialize()
+        return self.instance
+
+
+@dataclass
+class Completion:
+    rid: int
+    result: dict
+    best_spins: np.ndarray
+    arrival: float
+    admitted: float
+    finished: float
+    footprint: int
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def _round_up(x: int, m: int) -> int:
+    return (x + m - 1) // m * m
+
+
+def footprint_bytes(req: Request) -> int:
+    """Upper estimate of the device memory a request holds while it runs
+    (instance encodings plus solve workspace), from the library's layouts."""
+    inst, R, sc = req.instance, req.runs, req.schedule
+    N = inst.N
+    levels = sc.steps if sc.kind == "geometric" else int(math.ceil(sc.T_hi / sc.c_step)) + 1
+    if req.dense:
+        Np = _round_up(N, 128) + 128
+        Ke = _round_up(N, 128)
+        ldr = _round_up(R, 256)
+        inst_b = Np * Np * 4 + 8 * Ke * Ke + N * N * 8  # J fp32, digits, transient fixed point
+        if sc.precision == "bf16":
+            inst_b += Np * Np * 2
+            state = 2 * ldr * Np * 2
+        else:
+            state = 2 * Np * _round_up(R, 128) * 4
+        work = state + ldr * Ke + levels * ldr * 4 + (Ke // 128) * R * 16 + R * 64
+    else:
+        nnz = getattr(inst, "nnz", 2 * getattr(inst, "dim", 3) * N)
+        inst_b = nnz * 4 + N * 16
+        work = R * N + R * 64 + levels * 4
+    return int((inst_b + work) * 1.05) + (1 << 20)
+
+
+class Scheduler:
+    """Admission policy: FIFO by arrival, admit while a slot and memory are free.
+
+    A request larger than the whole budget is rejected (never admitted) rather
+    than blocking the queue forever."""
+
+    def __init__(self, hbm_budget: int, max_active: int):
+        self.budget = int(hbm_budget)
+        self.max_active = int(max_active)
+        self.in_use = 0
+        self.active = 0
+        self.queue: list = []  # heap of (arrival, rid, request)
+        self.rejected: list = []
+
+    def submit(self, req: Request):
+        if footprint_bytes(req) > self.budget:
+            self.rejected.append(req)
+            return
+        heapq.heappush(self.queue, (req.arrival, req.rid, req))
+
+    def admissible(self, now: float):
+        """Pop the requests that can start now (arrived, slot and memory free)."""
+        out = []
+        while self.queue and self.queue[0][0] <= now and self.active < self.max_active:
+            req = self.queue[0][2]
+            fp = footprint_bytes(req)
+            if self.in_use + fp > self.budget:
+                break  # FIFO: wait for memory rather than overtake
+            heapq.heappop(self.queue)
+            self.in_use += fp
+            self.active += 1
+            out.append((req, fp))
+        return out
+
+    def finish(self):
+        """A solve completed: its slot is free (its memory is freed later)."""
+        self.active -= 1
+
+    def free(self, fp: int):
+        """A finished request's device memory was released."""
+        self.in_use -= fp
+
+    def next_arrival(self):
+        return self.queue[0][0] if self.queue else None
+
+    def blocked_on_memory(self, now: float) -> bool:
+        return bool(self.queue) and self.queue[0][0] <= now and self.active < self.max_active
+
+
+# ---------------------------------------------------------------------------
+# GPU executor
+# ---------------------------------------------------------------------------
+
+
+class MarsServer:
+    """Runs a stream of requests with continuous batching on the current GPU."""
+
+    def __init__(self, hbm_budget: int | None = None, max_active: int = 8, n_streams: int = 4):
+        import torch
+
+        from . import mars as M
+
+        self.torch = torch
+        self.M = M
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget = int(free * 0.8)
+        self.hbm_budget = hbm_budget
+        self.max_active = max_active
+        # default-priority streams (torch creates them non-blocking)
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+
+    def run(self, requests, time_scale: float = 1.0, verbose: bool = False):
+        """Serve `requests` (arrival times in seconds, scaled by time_scale);
+        returns (completions, stats)."""
+        torch, M = self.torch, self.M
+        sched = Scheduler(self.hbm_budget, self.max_active)
+        for r in requests:
+            sched.submit(r)
+        running = []  # dicts: req, inst, event, outs, buf, fp, admitted, stream
+        graveyard = []  # finished instances awaiting release (frees synchronise the device)
+        done = []
+        stream_load = [0] * len(self.streams)
+        peak_running = 0
+        t0 = time.perf_counter()
+        while sched.queue or running:
+            now = (time.perf_counter() - t0) / time_scale
+            progressed = False
+            # retire finished requests
+            still = []
+            for job in running:
+                if job["event"].query():
+                    res = M.Instance.read_result(job["buf"])
+                    best = job["outs"]["best_spins"].cpu().numpy()
+                    fin = (time.perf_counter() - t0) / time_scale
+                    done.append(Completion(job["req"].rid, res, best, job["req"].arrival, job["admitted"], fin,
+                                           job["fp"]))
+                    graveyard.append((job["inst"], job["fp"]))
+                    sched.finish()
+                    stream_load[job["stream"]] -= 1
+                    progressed = True
+                else:
+                    still.append(job)
+            running = still
+            # release device memory only while nothing runs: a free synchronises
+            # the device, which would stall the running solves
+            if graveyard and not running:
+                for inst, fp in graveyard:
+                    inst.close()
+                    sched.free(fp)
+                graveyard = []
+                progressed = True
+            # admit
+            for req, fp in sched.admissible(now):
+                k = int(np.argmin(stream_load))
+                stream = self.streams[k]
+                inst = M.Instance.from_inputs(req.materialize())
+                buf = torch.empty(256, dtype=torch.uint8, pin_memory=True)
+                outs = inst.solve_async(req.runs, req.schedule, req.seed, buf, stream=stream)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                stream_load[k] += 1
+                running.append({"req": req, "inst": inst, "event": ev, "outs": outs, "buf": buf, "fp": fp,
+                                "admitted": (time.perf_counter() - t0) / time_scale, "stream": k})
+                if verbose:
+                    print("admit", req.rid, "N", req.N, "runs", req.runs, "stream", k, flush=True)
+                progressed = True
+            peak_running = max(peak_running, len(running))
+            if not progressed:
+                nxt = sched.next_arrival()
+                wait = 2e-4
+                if nxt is not None and not running:
+                    wait = max(0.0, min(0.05, (nxt - now) * time_scale))
+                time.sleep(wait)
+        for inst, fp in graveyard:
+            inst.close()
+            sched.free(fp)
+        makespan = (time.perf_counter() - t0) / time_scale
+        lat = np.array([c.latency for c in done]) if done else np.zeros(1)
+        updates = sum(int(c.result["spin_updates"]) for c in done)
+        stats = {"requests": len(done), "rejected": len(sched.rejected), "makespan_s": makespan,
+                 "peak_concurrent": peak_running,
+                 "spin_updates": updates, "spin_updates_per_s": updates / makespan if makespan > 0 else 0.0,
+                 "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+                 "latency_p99_ms": float(np.percentile(lat, 99) * 1e3)}
+        return sorted(done, key=lambda c: c.rid), stats
+
+
+# ---------------------------------------------------------------------------
+# the served mixed stream (shape of the paper's two workload families)
+# ---------------------------------------------------------------------------
+
+
+def mixed_stream(n_requests: int, rate: float, seed: int = 0, n_lo: int = 100, n_hi: int = 10000,
+                 runs_lo: int = 256, runs_hi: int = 4096, levels: int = 300):
+    """Poisson arrivals at `rate` requests/s; N log-uniform in [n_lo, n_hi];
+    half dense SK couplings N(0, 1/N) solved in the bf16 form, half
+    Erdos-Renyi average degree 4 with +-1 weights (J = -w) solved in fp32;
+    runs uniform in [runs_lo, runs_hi]; geometric schedules scaled to each
+    instance's field scale (sqrt(N * 1/N) = 1 for SK, sqrt(degree) for the
+    +-1 graphs)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for k in range(n_requests):
+        t += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+        N = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        runs = int(rng.integers(runs_lo, runs_hi + 1))
+        if k % 2 == 0:
+            spec = InstanceSpec("sk", N, seed * 100003 + k)
+            prec, s = "bf16", math.sqrt((N - 1) / N)
+        else:
+            spec = InstanceSpec("er", N, seed * 100003 + k)
+            prec, s = "fp32", math.sqrt(min(4.0, N - 1.0))
+        sch = I.Schedule(T_lo=0.25 * s, T_hi=1.5 * s, T_end=0.01 * s, steps=levels, phases=2, precision=prec)
+        reqs.append(Request(k, spec, runs, sch, seed=1000 + k, arrival=t))
+    return reqs

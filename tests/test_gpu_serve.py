@@ -1,0 +1,31 @@
+"""GPU check of the serving loop: requests that run concurrently on several
+streams give bit-for-bit the same results as the same requests solved alone,
+and the solves really overlapped."""
+import numpy as np
+import pytest
+
+from tests.gpu_common import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_equal_alone():
+    require_gpu()
+    from paper_1907_05124_amd import mars as M
+    from paper_1907_05124_amd import serve as S
+
+    reqs = S.mixed_stream(16, rate=500.0, seed=5, n_lo=100, n_hi=1500, runs_lo=256, runs_hi=1024, levels=60)
+    for r in reqs:
+        r.instance = r.materialize()
+    announce("serve mixed", len(reqs))
+    server = S.MarsServer(max_active=6, n_streams=4)
+    done, stats = server.run(reqs)
+    print(stats)
+    assert stats["requests"] == len(reqs) and stats["rejected"] == 0
+    assert stats["peak_concurrent"] >= 2
+    for c, r in zip(done, reqs):
+        assert c.rid == r.rid
+        with M.Instance.from_inputs(r.instance) as g:
+            alone = g.solve_ex(r.runs, r.schedule, r.seed, want_best=True)
+        assert alone["result"] == c.result, r.rid
+        assert np.array_equal(alone["best_spins"].cpu().numpy(), c.best_spins), r.rid

@@ -1,0 +1,80 @@
+"""CPU checks of the serving admission policy (no GPU): memory and slot
+limits are never exceeded, arrivals are served first-come first-served,
+oversized requests are rejected instead of blocking the queue, and every
+admissible request is eventually admitted."""
+import numpy as np
+
+from paper_1907_05124_amd import inputs as I
+from paper_1907_05124_amd import serve as S
+
+
+def _reqs(n, seed=0, rate=50.0):
+    return S.mixed_stream(n, rate, seed=seed, n_lo=50, n_hi=800, runs_lo=64, runs_hi=512, levels=20)
+
+
+def _simulate(reqs, budget, max_active, service=0.05):
+    """Discrete-event run of the scheduler with a fake executor (fixed service time)."""
+    sched = S.Scheduler(budget, max_active)
+    for r in reqs:
+        sched.submit(r)
+    t, running, order, peak_mem, peak_active = 0.0, [], [], 0, 0
+    while sched.queue or running:
+        for req, fp in sched.admissible(t):
+            running.append((t + service * (1 + req.N / 800), req, fp))
+            order.append(req.rid)
+        peak_mem = max(peak_mem, sched.in_use)
+        peak_active = max(peak_active, sched.active)
+        assert sched.in_use <= budget and sched.active <= max_active
+        nxt = [e for e, _, _ in running]
+        if sched.queue and sched.queue[0][0] > t:
+            nxt.append(sched.queue[0][0])  # the next arrival
+        assert nxt, "queue head arrived but was not admitted with nothing running"
+        t = min(nxt)
+        keep = []
+        for e, req, fp in running:
+            if e <= t:
+                sched.finish()
+                sched.free(fp)
+            else:
+                keep.append((e, req, fp))
+        running = keep
+    return order, peak_mem, peak_active, sched
+
+
+def test_limits_and_fifo():
+    reqs = _reqs(60)
+    budget = 4 * max(S.footprint_bytes(r) for r in reqs)
+    order, peak_mem, peak_active, sched = _simulate(reqs, budget, max_active=3)
+    assert sorted(order) == [r.rid for r in reqs]  # every request served
+    arrivals = {r.rid: r.arrival for r in reqs}
+    assert all(arrivals[a] <= arrivals[b] for a, b in zip(order, order[1:]))  # FIFO
+    assert peak_active <= 3 and peak_mem <= budget
+    assert not sched.rejected
+
+
+def test_oversized_request_is_rejected_not_blocking():
+    reqs = _reqs(10)
+    budget = max(S.footprint_bytes(r) for r in reqs) + 1
+    big = S.Request(999, S.InstanceSpec("sk", 4000, 1), 64, reqs[0].schedule, 1, arrival=0.0)
+    order, _, _, sched = _simulate(reqs + [big], budget, max_active=2)
+    assert [r.rid for r in sched.rejected] == [999]
+    assert sorted(order) == [r.rid for r in reqs]
+
+
+def test_footprint_grows_with_size():
+    base = S.Request(0, I.sk_instance(300, 1), 512, I.Schedule(steps=50, precision="bf16"), 1)
+    bigger_n = S.Request(1, I.sk_instance(600, 1), 512, base.schedule, 1)
+    more_runs = S.Request(2, base.instance, 2048, base.schedule, 1)
+    assert S.footprint_bytes(bigger_n) > S.footprint_bytes(base)
+    assert S.footprint_bytes(more_runs) > S.footprint_bytes(base)
+
+
+def test_mixed_stream_shape():
+    reqs = S.mixed_stream(200, 10.0, seed=3)
+    Ns = np.array([r.N for r in reqs])
+    assert Ns.min() >= 100 and Ns.max() <= 10000
+    assert abs(np.mean(np.log(Ns)) - (np.log(100) + np.log(10000)) / 2) < 0.5
+    kinds = [r.dense for r in reqs]
+    assert sum(kinds) == 100
+    gaps = np.diff([r.arrival for r in reqs])
+    assert np.all(gaps >= 0) and abs(gaps.mean() - 0.1) < 0.03
