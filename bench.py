@@ -23,7 +23,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "spin-updates/s (runs×N×steps) at equal best-energy gap; p50/p99 solve latency"
-PEAK = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s
+# TFLOP/s except hbm (GB/s).  *_valu: vector FMA without packed-fp32 issue
+# (the library is built without it): 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
+PEAK = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0, "fp32_valu": 78.6, "fp64_valu": 78.6}
 
 # HBM bytes of one dense phase launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # (KiB per dispatch, SK2000 workload), scaled by the counters' reading of a
@@ -230,22 +232,23 @@ def main():
         res = inst.solve_ex(R, sch, args.seed, want_best=True, sync=True, stream=stream)["result"]
         out = {"precision": prec, "ms_per_step": ms, "value": int(res["spin_updates"]) / (ms * 1e-3),
                "step_ms": step_ms, "result": res, "roofline": None}
-        if dense:
-            # dominant kernel: the field product of one phase.  Its average
-            # launch time is the solve time minus a solve with no levels (draws,
-            # rounding, energies, best-of-runs), divided by the number of phase
-            # launches, all timed with events on the same stream.
-            zero = sch.replace(steps=0)
-            reps = 3
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # solve with no levels (draws, rounding, energies, best-of-runs), timed
+        # with events on the same stream: the solve minus it is the time of
+        # the anneal kernels
+        zero = sch.replace(steps=0)
+        reps = 3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        solve(zero)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
             solve(zero)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            for _ in range(reps):
-                solve(zero)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            base_ms = e0.elapsed_time(e1) / reps
+        e1.record(stream)
+        torch.cuda.synchronize()
+        base_ms = e0.elapsed_time(e1) / reps
+        if dense:
+            # dominant kernel: the field product of one phase (one launch per
+            # phase and level)
             _, phases = inst.describe(sch)
             launches = sch.steps * phases
             per_launch_s = max(ms - base_ms, 1e-6) * 1e-3 / launches
@@ -259,6 +262,19 @@ def main():
                                "traffic": recorded_traffic(args.workload, prec),
                                "kernel": kname, "launch_us": round(per_launch_s * 1e6, 3),
                                "flops_per_launch": flops}
+        else:
+            # one launch of the LDS-resident solver holds the whole anneal; its
+            # algorithmic work is 2 flops per coupling term: sweeps x nnz terms
+            lat = isinstance(w.instance, I.LatticeInstance)
+            nnz = 2 * w.instance.dim * N if lat else w.instance.nnz
+            per_launch_s = max(ms - base_ms, 1e-6) * 1e-3
+            flops = 2.0 * float(res["sweeps_executed"]) * nnz
+            achieved = flops / per_launch_s / 1e12
+            peak = PEAK["fp64_valu"] if prec == "fp64" else PEAK["fp32_valu"]
+            out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                               "frac": round(achieved / peak, 4), "traffic": None,
+                               "kernel": "k_lattice_solve" if lat else "k_sparse_solve",
+                               "launch_us": round(per_launch_s * 1e6, 3), "flops_per_launch": flops}
         return out
 
     measured = {p: measure(p) for p in forms}

@@ -10,8 +10,9 @@
 // the buffer being written this sweep, the rest from the previous one.
 //
 // Workgroup tile BM runs x BN spins, K in 64-element slabs through
-// double-buffered LDS (rows padded to 72 elements), WM x WN waves, each wave
-// (BM/WM) x (BN/WN) made of 32 x 32 blocks of the 32x32x16 bf16 MFMA.
+// double-buffered LDS (rows padded to 72 elements) fed from a register ring
+// of PF slabs, WM x WN waves, each wave (BM/WM) x (BN/WN) made of 32 x 32
+// blocks of the 32x32x16 bf16 MFMA.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,7 +37,18 @@ __device__ inline unsigned short float_to_bf16(float f)
     return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
-template <int BM, int BN, int WM, int WN>
+// tanh(a) = 1 - 2 / (exp(2a) + 1) on |a| with the hardware exp2 and
+// reciprocal, sign restored afterwards; absolute error ~1e-7, far below the
+// bf16 rounding of the result (2^-9)
+__device__ inline float bf16_form_tanh(float x)
+{
+    const float a = fabsf(x);
+    const float e = __builtin_amdgcn_exp2f(a * 2.8853900817779268f);
+    const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+    return copysignf(t, x);
+}
+
+template <int BM, int BN, int WM, int WN, int PF>
 __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
     const unsigned short *__restrict__ J, int ldj, const unsigned short *__restrict__ Mold,
     unsigned short *__restrict__ Mnew, int ldk, int R, int p0, int p1, int nrt, int nct, int kpad,
@@ -48,6 +60,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
     constexpr int CA = BM * HBK / 8, CB = BN * HBK / 8;  // 16-byte chunks per slab
     constexpr int LA = (CA + NT - 1) / NT, LB = (CB + NT - 1) / NT;
     static_assert(MB >= 1 && NB >= 1, "tile shape");
+    static_assert(PF >= 1 && PF <= 4, "prefetch ring");
 
     __shared__ __attribute__((aligned(16))) unsigned short As[2][BM][HLD];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN][HLD];
@@ -75,7 +88,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
             for (int v = 0; v < 16; ++v)
                 acc[a][b][v] = 0.0f;
 
-    ushortx8 ga[LA], gb[LB];
+    ushortx8 ga[PF][LA], gb[PF][LB];
     // A chunk: run row, 8 spins; spins below p0 from the new buffer, a chunk
     // straddling p0 is blended element by element
     auto load_a = [&](ushortx8 &dst, int c, int k0) {
@@ -93,61 +106,76 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
                 dst[e] = (kc + e < p0) ? x[e] : y[e];
         }
     };
-#define H_LOAD(k0)                                                                                  \
+#define H_LOAD(RA, RB, k0)                                                                          \
     _Pragma("unroll") for (int q = 0; q < LA; ++q)                                                  \
     {                                                                                               \
         const int c_ = tid + q * NT;                                                                \
         if (c_ < CA)                                                                                \
-            load_a(ga[q], c_, (k0));                                                                \
+            load_a((RA)[q], c_, (k0));                                                              \
     }                                                                                               \
     _Pragma("unroll") for (int q = 0; q < LB; ++q)                                                  \
     {                                                                                               \
         const int c_ = tid + q * NT;                                                                \
         if (c_ < CB)                                                                                \
-            gb[q] = *reinterpret_cast<const ushortx8 *>(J + (size_t)(i0 + (c_ >> 3)) * ldj + (k0) + (c_ & 7) * 8); \
+            (RB)[q] = *reinterpret_cast<const ushortx8 *>(J + (size_t)(i0 + (c_ >> 3)) * ldj + (k0) + (c_ & 7) * 8); \
     }
-#define H_STORE(buf)                                                                                \
+#define H_STORE(RA, RB, buf)                                                                        \
     _Pragma("unroll") for (int q = 0; q < LA; ++q)                                                  \
     {                                                                                               \
         const int c_ = tid + q * NT;                                                                \
         if (c_ < CA)                                                                                \
-            *reinterpret_cast<ushortx8 *>(&As[(buf)][c_ >> 3][(c_ & 7) * 8]) = ga[q];               \
+            *reinterpret_cast<ushortx8 *>(&As[(buf)][c_ >> 3][(c_ & 7) * 8]) = (RA)[q];             \
     }                                                                                               \
     _Pragma("unroll") for (int q = 0; q < LB; ++q)                                                  \
     {                                                                                               \
         const int c_ = tid + q * NT;                                                                \
         if (c_ < CB)                                                                                \
-            *reinterpret_cast<ushortx8 *>(&Bs[(buf)][c_ >> 3][(c_ & 7) * 8]) = gb[q];               \
+            *reinterpret_cast<ushortx8 *>(&Bs[(buf)][c_ >> 3][(c_ & 7) * 8]) = (RB)[q];             \
     }
 
+    // Slabs move global -> registers -> LDS.  Registers hold a ring of PF
+    // slabs: at step kt the ring slot of slab kt (already in LDS) is refilled
+    // with slab kt + PF, the step computes on slab kt, then slab kt + 1 goes
+    // from its ring slot into the other LDS buffer.  A load thus has PF
+    // compute steps to arrive.
     const int nk = kpad / HBK;
-    H_LOAD(0);
-    H_STORE(0);
+#pragma unroll
+    for (int s = 0; s < PF; ++s)
+        if (s < nk) {
+            H_LOAD(ga[s], gb[s], s * HBK);
+        }
+    H_STORE(ga[0], gb[0], 0);
     __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) {
-            H_LOAD((kt + 1) * HBK);
+    for (int kb = 0; kb < nk; kb += PF) {
+#pragma unroll
+        for (int s = 0; s < PF; ++s) {
+            const int kt = kb + s;
+            if (kt < nk) {
+                const int cur = kt & 1;
+                if (kt + PF < nk) {
+                    H_LOAD(ga[s], gb[s], (kt + PF) * HBK);
+                }
+#pragma unroll
+                for (int ks = 0; ks < HBK / 16; ++ks) {
+                    bf16x8 fa[MB], fb[NB];
+#pragma unroll
+                    for (int a = 0; a < MB; ++a)
+                        fa[a] = *reinterpret_cast<const bf16x8 *>(&As[cur][wm * TM + a * 32 + li][ks * 16 + kh * 8]);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        fb[b] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][wn * TN + b * 32 + li][ks * 16 + kh * 8]);
+#pragma unroll
+                    for (int a = 0; a < MB; ++a)
+#pragma unroll
+                        for (int b = 0; b < NB; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                }
+                if (kt + 1 < nk) {
+                    H_STORE(ga[(s + 1) % PF], gb[(s + 1) % PF], cur ^ 1);
+                }
+                __syncthreads();
+            }
         }
-#pragma unroll
-        for (int ks = 0; ks < HBK / 16; ++ks) {
-            bf16x8 fa[MB], fb[NB];
-#pragma unroll
-            for (int a = 0; a < MB; ++a)
-                fa[a] = *reinterpret_cast<const bf16x8 *>(&As[cur][wm * TM + a * 32 + li][ks * 16 + kh * 8]);
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                fb[b] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][wn * TN + b * 32 + li][ks * 16 + kh * 8]);
-#pragma unroll
-            for (int a = 0; a < MB; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
-        }
-        if (kt + 1 < nk) {
-            H_STORE(cur ^ 1);
-        }
-        __syncthreads();
     }
 #undef H_LOAD
 #undef H_STORE
@@ -174,7 +202,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
                         float phi = acc[a][b][v];
                         if (hhalf)
                             phi += hhalf[spin];
-                        const float th = tanhf(phi * it);
+                        const float th = bf16_form_tanh(phi * it);
                         nw = damp ? (1.0f - gamma) * old + gamma * th : th;
                     }
                     const unsigned short nb16 = float_to_bf16(nw);

@@ -8,7 +8,7 @@
 namespace mars {
 
 // Tile shape measured fastest on the SK N=2000 x 4096-run phase shape.
-constexpr int HBM_ = 128, HBN_ = 128, HWM = 4, HWN = 4;
+constexpr int HBM_ = 128, HBN_ = 128, HWM = 4, HWN = 4, HPF = 1;
 
 __global__ void k_bf16_from_f32(const float *J, size_t n, unsigned short *Jb)
 {
@@ -57,7 +57,7 @@ void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsi
     const int nrt = (R + HBM_ - 1) / HBM_;
     const int nct = (p1 - p0 + HBN_ - 1) / HBN_;
     const int kpad = (I.N + HBK - 1) / HBK * HBK;
-    k_dense_phase_bf16<HBM_, HBN_, HWM, HWN><<<nrt * nct, 64 * HWM * HWN, 0, s>>>(
+    k_dense_phase_bf16<HBM_, HBN_, HWM, HWN, HPF><<<nrt * nct, 64 * HWM * HWN, 0, s>>>(
         I.Jbf, I.Np, Mold, Mnew, ldk, R, p0, p1, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma, dmax);
 }
 

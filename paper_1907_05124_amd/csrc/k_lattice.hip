@@ -1,0 +1,348 @@
+// Periodic +-J lattices: a workgroup anneals a block of rpw runs from start
+// to finish with their magnetisations in LDS, m[site * rpw + q], as the
+// sparse solver does, specialised for the stencil:
+//  * each thread updates one site for VEC consecutive runs, so the site's
+//    address, neighbour offsets and bond byte are shared by VEC updates and
+//    the VEC values of a neighbour arrive in one LDS read;
+//  * the thread owns a fixed x half-column slot, walks rows (y, z) with a
+//    constant stride and keeps the site index incrementally; neighbour
+//    offsets along y and z are constants of the row;
+//  * checkerboard phases (colour = parity of x + y + z) are independent sets,
+//    updated in place with a barrier between them; the synchronous variant
+//    writes a second copy and swaps.
+#include <algorithm>
+#include <cmath>
+
+#include "common_device.h"
+#include "lds_state.h"
+#include "mars_internal.h"
+
+namespace mars {
+
+template <typename S, int VEC, int DIM, bool JAC, bool TRACKD, bool HAS_H>
+__global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
+{
+    typedef typename LStore<S>::C C;
+    extern __shared__ unsigned char smem_raw[];
+    const int N = a.N;
+    const int rpw = 1 << lg_rpw;
+    S *m = reinterpret_cast<S *>(smem_raw);
+    S *m2 = JAC ? m + (size_t)N * rpw : m;
+    const size_t state_bytes = ((size_t)N * rpw * sizeof(S) * (JAC ? 2 : 1) + 15) & ~(size_t)15;
+    RunState *rsl = reinterpret_cast<RunState *>(smem_raw + state_bytes);
+    uint32_t *dq = reinterpret_cast<uint32_t *>(rsl + rpw);
+
+    const int nq = rpw / VEC;               // run groups per workgroup
+    const int qg = threadIdx.x % nq;
+    const int q0 = qg * VEC;                // first run slot of this thread
+    const int tq = threadIdx.x / nq;        // thread index within the run group
+    const int Tq = blockDim.x / nq;
+    const int run0 = blockIdx.x * rpw + q0;
+
+    bool live[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+        live[e] = run0 + e < a.R;
+
+    // initial state (Algorithm 1: s_i := rand(-1, 1))
+    for (int i = tq; i < N; i += Tq) {
+        Pack<S, VEC> p;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            C v = 0;
+            if (live[e])
+                v = a.m0 ? (C)(reinterpret_cast<const C *>(a.m0))[(size_t)i * a.R + run0 + e]
+                         : (C)draw_m0(a.seed, run0 + e, i);
+            p.v[e] = LStore<S>::st(v);
+        }
+        lds_put<S, VEC>(&m[((size_t)i << lg_rpw) + q0], p);
+    }
+    for (int q = threadIdx.x; q < rpw; q += blockDim.x) {
+        const int r = blockIdx.x * rpw + q;
+        rsl[q].start(a.rs, r < a.R ? a.T0[r] : 1.0, r < a.R);
+        dq[q] = 0;
+    }
+    const C g = (C)a.damping;
+    const bool damp = a.damping != 1.0;
+
+    const int L0 = a.L0, L1 = a.L1, L2 = a.L2;
+    const int plane = L0 * L1, vol = plane * L2;
+    const int H = L0 / 2;
+    const uint8_t *__restrict__ bonds = a.bondbits;
+    int lgs = lg_rpw;  // log2 of the byte stride of one site
+    for (int sz = (int)sizeof(S); sz > 1; sz >>= 1)
+        ++lgs;
+    // byte offset (mod 2^32) of a site displacement
+    auto ob = [&](int d) -> uint32_t { return (uint32_t)d << lgs; };
+    // Column walk (when the threads of a run group cover whole planes of one
+    // colour): the thread owns the x slot xh of row y in every kz-th plane,
+    // so its x and y neighbour offsets are fixed and only z wraps.  Otherwise
+    // the thread walks rows with a constant stride.
+    const bool cols = (Tq % (H * L1)) == 0;
+    const int xh = tq % H;
+    const int kz = cols ? Tq / (H * L1) : 0;
+    const int cy = cols ? (tq / H) % L1 : 0;
+    const int cz0 = cols ? tq / (H * L1) : 0;
+    const int row0 = tq / H;
+    const int drow = Tq / H;
+    const int nrows = L1 * L2;
+    const int dy = drow % L1, dz = drow / L1;
+    // x offsets by parity p of x: p = 0 has x + 1 inside the row, p = 1 has x - 1
+    const uint32_t oxp0 = ob(1), oxm0 = ob(xh > 0 ? -1 : L0 - 1);
+    const uint32_t oxp1 = ob(xh < H - 1 ? 1 : 1 - L0), oxm1 = ob(-1);
+    const uint32_t cyp = ob(cy + 1 < L1 ? L0 : L0 - plane), cym = ob(cy > 0 ? -L0 : plane - L0);
+
+    __syncthreads();
+    for (;;) {
+        // the runs' level state, advanced at the end of the previous sweep
+        C scale[VEC];
+        bool done[VEC];
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            scale[e] = run_scale<C>(rsl[q0 + e]);
+            done[e] = rsl[q0 + e].done != 0;
+            any |= !done[e];
+        }
+        if (!__syncthreads_or(any))
+            break;
+        C dloc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            dloc[e] = 0;
+        const unsigned char *mb = reinterpret_cast<const unsigned char *>(m) + q0 * sizeof(S);
+        unsigned char *wb = reinterpret_cast<unsigned char *>(JAC ? m2 : m) + q0 * sizeof(S);
+        // update site v at LDS byte offset vb (from the thread's run slot);
+        // o*: byte offsets of its neighbours along +x, -x, +y, -y, +z, -z
+        auto site = [&](int v, uint32_t vb, uint32_t oxp, uint32_t oxm, uint32_t oyp, uint32_t oym, uint32_t ozp,
+                        uint32_t ozm) {
+            const uint32_t b = bonds[v];
+            C phi[VEC];
+            if constexpr (sizeof(S) == 2 && VEC == 2) {
+                // packed pair of fp16 runs: one 32-bit read per neighbour, the
+                // bond's sign applied to both halves with one xor
+                auto rd = [&](uint32_t o) -> uint32_t {
+                    return *reinterpret_cast<const uint32_t *>(mb + (uint32_t)(vb + o));
+                };
+                auto sgn = [&](int k) -> uint32_t {
+                    return (uint32_t)__builtin_amdgcn_sbfe((int)b, k, 1) & 0x80008000u;
+                };
+                auto lo = [](uint32_t u) -> float {
+                    return (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xffffu));
+                };
+                auto hi = [](uint32_t u) -> float {
+                    return (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
+                };
+                const uint32_t u0 = rd(oxp) ^ sgn(0), u1 = rd(oxm) ^ sgn(1);
+                const uint32_t u2 = rd(oyp) ^ sgn(2), u3 = rd(oym) ^ sgn(3);
+                float p0 = lo(u0), p1 = hi(u0);
+                p0 += lo(u1);
+                p1 += hi(u1);
+                p0 += lo(u2);
+                p1 += hi(u2);
+                p0 += lo(u3);
+                p1 += hi(u3);
+                if (DIM == 3) {
+                    const uint32_t u4 = rd(ozp) ^ sgn(4), u5 = rd(ozm) ^ sgn(5);
+                    p0 += lo(u4);
+                    p1 += hi(u4);
+                    p0 += lo(u5);
+                    p1 += hi(u5);
+                }
+                phi[0] = p0;
+                phi[1] = p1;
+            } else {
+                auto get = [&](uint32_t o) {
+                    return lds_get<S, VEC>(reinterpret_cast<const S *>(mb + (uint32_t)(vb + o)));
+                };
+                const Pack<S, VEC> t0 = get(oxp), t1 = get(oxm), t2 = get(oyp), t3 = get(oym);
+                const C s0 = (b & 1) ? (C)-1 : (C)1, s1 = (b & 2) ? (C)-1 : (C)1;
+                const C s2 = (b & 4) ? (C)-1 : (C)1, s3 = (b & 8) ? (C)-1 : (C)1;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    C f = s0 * LStore<S>::ld(t0.v[e]);
+                    f += s1 * LStore<S>::ld(t1.v[e]);
+                    f += s2 * LStore<S>::ld(t2.v[e]);
+                    f += s3 * LStore<S>::ld(t3.v[e]);
+                    phi[e] = f;
+                }
+                if (DIM == 3) {
+                    const Pack<S, VEC> t4 = get(ozp), t5 = get(ozm);
+                    const C s4 = (b & 16) ? (C)-1 : (C)1, s5 = (b & 32) ? (C)-1 : (C)1;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        phi[e] += s4 * LStore<S>::ld(t4.v[e]) + s5 * LStore<S>::ld(t5.v[e]);
+                }
+            }
+            if (HAS_H) {
+                C hh;
+                if constexpr (sizeof(C) == 8)
+                    hh = a.hhalf64[v];
+                else
+                    hh = a.hhalf32[v];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    phi[e] += hh;
+            }
+            const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + vb));
+            Pack<S, VEC> nw;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                const C th = l_tanh(l_apply(phi[e], scale[e]));
+                const C o = LStore<S>::ld(old.v[e]);
+                C n = damp ? ((C)1 - g) * o + g * th : th;
+                n = done[e] ? o : n;  // a finished run keeps its state
+                nw.v[e] = done[e] ? old.v[e] : LStore<S>::st(n);
+                const C dd = n > o ? n - o : o - n;
+                dloc[e] = dd > dloc[e] ? dd : dloc[e];
+            }
+            lds_put<S, VEC>(reinterpret_cast<S *>(wb + vb), nw);
+        };
+        for (int c = 0; c < (JAC ? 1 : 2); ++c) {
+            if (cols) {
+                // site and byte offset carried along the column
+                int v0 = L0 * (cy + L1 * cz0) + 2 * xh;
+                uint32_t vb0 = ob(v0);
+                const int dv = kz * plane;
+                const uint32_t dvb = ob(dv);
+                for (int z = cz0; z < L2; z += kz, v0 += dv, vb0 += dvb) {
+                    const uint32_t ozp = ob(z + 1 < L2 ? plane : plane - vol);
+                    const uint32_t ozm = ob(z > 0 ? -plane : vol - plane);
+#pragma unroll
+                    for (int pp = 0; pp < (JAC ? 2 : 1); ++pp) {
+                        const int p = JAC ? pp : ((c + cy + z) & 1);
+                        site(v0 + p, vb0 + (p ? oxp0 : 0u), p ? oxp1 : oxp0, p ? oxm1 : oxm0, cyp, cym, ozp, ozm);
+                    }
+                }
+            } else {
+                int y = row0 % L1, z = row0 / L1;
+                for (int rw = row0; rw < nrows; rw += drow) {
+                    const uint32_t oyp = ob(y + 1 < L1 ? L0 : L0 - plane), oym = ob(y > 0 ? -L0 : plane - L0);
+                    const uint32_t ozp = ob(z + 1 < L2 ? plane : plane - vol);
+                    const uint32_t ozm = ob(z > 0 ? -plane : vol - plane);
+#pragma unroll
+                    for (int pp = 0; pp < (JAC ? 2 : 1); ++pp) {
+                        const int p = JAC ? pp : ((c + y + z) & 1);
+                        const int v = L0 * rw + 2 * xh + p;
+                        site(v, ob(v), p ? oxp1 : oxp0, p ? oxm1 : oxm0, oyp, oym, ozp, ozm);
+                    }
+                    y += dy;
+                    z += dz;
+                    if (y >= L1) {
+                        y -= L1;
+                        ++z;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (JAC) {
+            S *tmp = m;
+            m = m2;
+            m2 = tmp;
+        }
+        if (TRACKD) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (!done[e])
+                    atomicMax(&dq[q0 + e], __float_as_uint((float)dloc[e]));
+            __syncthreads();
+        }
+        if (tq == 0) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                rsl[q0 + e].end_sweep(a.rs, __uint_as_float(dq[q0 + e]), TRACKD, a.max_sweeps, a.d_min);
+                dq[q0 + e] = 0;
+            }
+        }
+        __syncthreads();
+    }
+
+    // outputs: rounded spins (s = +1 if m >= 0), optional final magnetisation
+    for (int i = tq; i < N; i += Tq) {
+        const Pack<S, VEC> p = lds_get<S, VEC>(&m[((size_t)i << lg_rpw) + q0]);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            if (!live[e])
+                continue;
+            const C v = LStore<S>::ld(p.v[e]);
+            a.spins[(size_t)(run0 + e) * N + i] = (v >= (C)0) ? 1 : -1;
+            if (a.m_final)
+                reinterpret_cast<C *>(a.m_final)[(size_t)i * a.R + run0 + e] = v;
+        }
+    }
+    if (tq == 0)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            if (live[e])
+                rsl[q0 + e].write_stats(a.runstat, run0 + e);
+}
+
+template <typename S, int VEC, int DIM, bool HAS_H>
+static void (*lat_pick3(bool jac, bool trackd))(GraphArgs, int)
+{
+    if (jac)
+        return trackd ? k_lattice_solve<S, VEC, DIM, true, true, HAS_H> : k_lattice_solve<S, VEC, DIM, true, false, HAS_H>;
+    return trackd ? k_lattice_solve<S, VEC, DIM, false, true, HAS_H> : k_lattice_solve<S, VEC, DIM, false, false, HAS_H>;
+}
+
+template <typename S, int VEC, bool HAS_H>
+static void (*lat_pick(int dim, bool jac, bool trackd))(GraphArgs, int)
+{
+    return dim == 3 ? lat_pick3<S, VEC, 3, HAS_H>(jac, trackd) : lat_pick3<S, VEC, 2, HAS_H>(jac, trackd);
+}
+
+template <typename S, int VEC>
+static hipError_t lat_launch(const GraphArgs &a, int lg_rpw, bool jac, bool trackd, dim3 grid, dim3 block,
+                             size_t lds, hipStream_t s)
+{
+    const bool has_h = a.hhalf32 != nullptr;
+    void (*fn)(GraphArgs, int) =
+        has_h ? lat_pick<S, VEC, true>(a.dim, jac, trackd) : lat_pick<S, VEC, false>(a.dim, jac, trackd);
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(fn, grid, block, lds, s, a, lg_rpw);
+    return hipGetLastError();
+}
+
+// esz: bytes per stored magnetisation; rpw: runs per workgroup (power of two)
+hipError_t launch_lattice_solve(const GraphArgs &a, int esz, int rpw, bool jac, bool trackd, hipStream_t s)
+{
+    int lg = 0;
+    while ((1 << lg) < rpw)
+        ++lg;
+    const int vec = (rpw >= 2 && esz <= 4) ? 2 : 1;
+    const int nq = rpw / vec;
+    const int H = a.L0 / 2;
+    const int N = a.N;
+    const size_t per_run = (size_t)N * esz * (jac ? 2 : 1);
+    const size_t lds = (((size_t)rpw * per_run + 15) & ~(size_t)15) + rpw * RUN_AREA_BYTES;
+    // threads per run group, at most 1024 per workgroup: whole planes of one
+    // colour (H x L1 sites) when one fits, so that threads walk columns along
+    // z; otherwise a multiple of the half-row length H, no more than one per
+    // site of a colour
+    int Tq;
+    const int P = H * a.L1;
+    if (P <= 1024 / nq) {
+        Tq = P * std::min(a.L2, (1024 / nq) / P);
+    } else {
+        Tq = std::min(1024 / nq, std::max(H, (N / 2 + H - 1) / H * H));
+        Tq = std::max(H, Tq / H * H);
+    }
+    if (Tq * nq > 1024)
+        return hipErrorInvalidConfiguration;
+    dim3 grid((a.R + rpw - 1) / rpw), block(Tq * nq);
+    if (esz == 8)
+        return lat_launch<double, 1>(a, lg, jac, trackd, grid, block, lds, s);
+    if (esz == 4)
+        return vec == 2 ? lat_launch<float, 2>(a, lg, jac, trackd, grid, block, lds, s)
+                        : lat_launch<float, 1>(a, lg, jac, trackd, grid, block, lds, s);
+    return vec == 2 ? lat_launch<_Float16, 2>(a, lg, jac, trackd, grid, block, lds, s)
+                    : lat_launch<_Float16, 1>(a, lg, jac, trackd, grid, block, lds, s);
+}
+
+}  // namespace mars

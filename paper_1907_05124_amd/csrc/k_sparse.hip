@@ -1,0 +1,261 @@
+// Sparse (CSR-defined) instances: a workgroup anneals a block of rpw runs
+// from start to finish with their magnetisations in LDS, m[slot * rpw + q],
+// in the sliced-ELL labelling built at creation (colour classes contiguous,
+// each sorted by degree and padded to whole slices of SELL_H slots).
+//  * A colour class is an independent set (no coupling inside it), so its
+//    slots are updated in place; classes run in colour order with a barrier
+//    between them (sequential dynamics in colour order).  The synchronous
+//    variant writes a second copy and swaps after each sweep.
+//  * Each thread updates one slot for VEC consecutive runs: one entry read
+//    (neighbour slot and weight) serves VEC terms, and the VEC values of a
+//    neighbour arrive in one LDS read.
+//  * The threads of a wave cover consecutive slots, so their entry reads
+//    (column j of a slice) are consecutive words.
+//  * Missing entries of a slice point at the all-zero row nslot, so every
+//    lane of a slice runs the same number of terms.
+//  * With +-1 weights the weight is rebuilt as +-1.0f from the entry's sign
+//    bit (one bit operation) instead of an integer-to-float conversion.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+#include "common_device.h"
+#include "lds_state.h"
+#include "mars_internal.h"
+
+namespace mars {
+
+template <typename C, bool UNIT>
+__device__ inline C entry_weight(uint32_t cb)
+{
+    if constexpr (UNIT && sizeof(C) == 4)
+        return __uint_as_float((cb & 0x80000000u) | 0x3f800000u);
+    else
+        return (C)((int32_t)cb >> 24);
+}
+
+template <typename S, int VEC, bool JAC, bool TRACKD, bool HAS_H, bool UNIT>
+__global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
+{
+    typedef typename LStore<S>::C C;
+    extern __shared__ unsigned char smem_raw[];
+    const int N = a.N;
+    const int ns = a.nslot;
+    const int rows = ns + 1;  // row ns: all zeros
+    const int rpw = 1 << lg_rpw;
+    S *m = reinterpret_cast<S *>(smem_raw);
+    S *m2 = JAC ? m + (size_t)rows * rpw : m;
+    const size_t state_bytes = ((size_t)rows * rpw * sizeof(S) * (JAC ? 2 : 1) + 15) & ~(size_t)15;
+    RunState *rsl = reinterpret_cast<RunState *>(smem_raw + state_bytes);
+    uint32_t *dq = reinterpret_cast<uint32_t *>(rsl + rpw);
+
+    const int nq = rpw / VEC;
+    const int qg = threadIdx.x % nq;
+    const int q0 = qg * VEC;
+    const int tq = threadIdx.x / nq;
+    const int Tq = blockDim.x / nq;
+    const int run0 = blockIdx.x * rpw + q0;
+
+    // initial state (Algorithm 1: s_i := rand(-1, 1)); padding slots and the
+    // zero row hold 0 in both copies
+    for (int i = tq; i < rows; i += Tq) {
+        const int v = i < ns ? a.perm[i] : -1;
+        Pack<S, VEC> p;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            C x = 0;
+            if (v >= 0 && run0 + e < a.R)
+                x = a.m0 ? (C)(reinterpret_cast<const C *>(a.m0))[(size_t)v * a.R + run0 + e]
+                         : (C)draw_m0(a.seed, run0 + e, v);
+            p.v[e] = LStore<S>::st(x);
+        }
+        lds_put<S, VEC>(&m[((size_t)i << lg_rpw) + q0], p);
+        if (JAC)
+            lds_put<S, VEC>(&m2[((size_t)i << lg_rpw) + q0], p);
+    }
+    for (int q = threadIdx.x; q < rpw; q += blockDim.x) {
+        const int r = blockIdx.x * rpw + q;
+        rsl[q].start(a.rs, r < a.R ? a.T0[r] : 1.0, r < a.R);
+        dq[q] = 0;
+    }
+    const C g = (C)a.damping;
+    const bool damp = a.damping != 1.0;
+    int lgs = lg_rpw;  // log2 of the byte stride of one slot's row
+    for (int sz = (int)sizeof(S); sz > 1; sz >>= 1)
+        ++lgs;
+    const uint32_t *__restrict__ colsell = a.colsell;
+    const int32_t *__restrict__ meta = a.sl_meta;
+
+    __syncthreads();
+    for (;;) {
+        // the runs' level state, advanced at the end of the previous sweep
+        C scale[VEC];
+        bool done[VEC];
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            scale[e] = run_scale<C>(rsl[q0 + e]);
+            done[e] = rsl[q0 + e].done != 0;
+            any |= !done[e];
+        }
+        if (!__syncthreads_or(any))
+            break;
+        C dloc[VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            dloc[e] = 0;
+        const int nph = JAC ? 1 : a.nphase;
+        for (int c = 0; c < nph; ++c) {
+            // the synchronous sweep visits every slot (padding slots are inert:
+            // no terms, zero field, state 0)
+            const int sb = JAC ? 0 : a.cls[2 * c];
+            const int sn = JAC ? ns : a.cls[2 * c + 1];
+            const unsigned char *mb = reinterpret_cast<const unsigned char *>(m) + q0 * sizeof(S);
+            unsigned char *wb = reinterpret_cast<unsigned char *>(JAC ? m2 : m) + q0 * sizeof(S);
+            for (int it = tq; it < sn; it += Tq) {
+                const int slot = sb + it;
+                const int off = meta[2 * (slot / SELL_H)];
+                const int w = meta[2 * (slot / SELL_H) + 1];
+                const uint32_t *cp = colsell + off + (slot % SELL_H);
+                C phi[VEC];
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    phi[e] = 0;
+#pragma unroll 4
+                for (int j = 0; j < w; ++j) {
+                    const uint32_t cb = cp[j * SELL_H];
+                    const C wt = entry_weight<C, UNIT>(cb);
+                    const Pack<S, VEC> t =
+                        lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((cb & 0xffffffu) << lgs)));
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        phi[e] += wt * LStore<S>::ld(t.v[e]);
+                }
+                if (HAS_H) {
+                    C hh;
+                    if constexpr (sizeof(C) == 8)
+                        hh = a.hhalf64[slot];
+                    else
+                        hh = a.hhalf32[slot];
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        phi[e] += hh;
+                }
+                const uint32_t o_slot = (uint32_t)slot << lgs;
+                const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + o_slot));
+                Pack<S, VEC> nw;
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const C th = l_tanh(l_apply(phi[e], scale[e]));
+                    const C o = LStore<S>::ld(old.v[e]);
+                    C n = damp ? ((C)1 - g) * o + g * th : th;
+                    n = done[e] ? o : n;  // a finished run keeps its state
+                    nw.v[e] = done[e] ? old.v[e] : LStore<S>::st(n);
+                    const C dd = n > o ? n - o : o - n;
+                    dloc[e] = dd > dloc[e] ? dd : dloc[e];
+                }
+                lds_put<S, VEC>(reinterpret_cast<S *>(wb + o_slot), nw);
+            }
+            __syncthreads();
+        }
+        if (JAC) {
+            S *tmp = m;
+            m = m2;
+            m2 = tmp;
+        }
+        if (TRACKD) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (!done[e])
+                    atomicMax(&dq[q0 + e], __float_as_uint((float)dloc[e]));
+            __syncthreads();
+        }
+        if (tq == 0) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                rsl[q0 + e].end_sweep(a.rs, __uint_as_float(dq[q0 + e]), TRACKD, a.max_sweeps, a.d_min);
+                dq[q0 + e] = 0;
+            }
+        }
+        __syncthreads();
+    }
+
+    // outputs in the caller's labels: rounded spins (s = +1 if m >= 0) and the
+    // optional final magnetisation
+    for (int i = tq; i < ns; i += Tq) {
+        const int v = a.perm[i];
+        if (v < 0)
+            continue;
+        const Pack<S, VEC> p = lds_get<S, VEC>(&m[((size_t)i << lg_rpw) + q0]);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            if (run0 + e >= a.R)
+                continue;
+            const C x = LStore<S>::ld(p.v[e]);
+            a.spins[(size_t)(run0 + e) * N + v] = (x >= (C)0) ? 1 : -1;
+            if (a.m_final)
+                reinterpret_cast<C *>(a.m_final)[(size_t)v * a.R + run0 + e] = x;
+        }
+    }
+    if (tq == 0)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            if (run0 + e < a.R)
+                rsl[q0 + e].write_stats(a.runstat, run0 + e);
+}
+
+typedef void (*SparseFn)(GraphArgs, int);
+
+template <typename S, int VEC, bool HAS_H, bool UNIT>
+static SparseFn sp_pick(bool jac, bool trackd)
+{
+    if (jac)
+        return trackd ? k_sparse_solve<S, VEC, true, true, HAS_H, UNIT> : k_sparse_solve<S, VEC, true, false, HAS_H, UNIT>;
+    return trackd ? k_sparse_solve<S, VEC, false, true, HAS_H, UNIT> : k_sparse_solve<S, VEC, false, false, HAS_H, UNIT>;
+}
+
+template <typename S, int VEC>
+static SparseFn sp_pick_hu(bool has_h, bool unit, bool jac, bool trackd)
+{
+    if (has_h)
+        return unit ? sp_pick<S, VEC, true, true>(jac, trackd) : sp_pick<S, VEC, true, false>(jac, trackd);
+    return unit ? sp_pick<S, VEC, false, true>(jac, trackd) : sp_pick<S, VEC, false, false>(jac, trackd);
+}
+
+// esz: bytes per stored magnetisation; rpw: runs per workgroup (power of two);
+// Tq: threads per run group; vec: runs per thread (1, 2 or 4, dividing rpw)
+hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, bool jac, bool trackd,
+                               bool unit, hipStream_t s)
+{
+    int lg = 0;
+    while ((1 << lg) < rpw)
+        ++lg;
+    const bool has_h = a.hhalf32 != nullptr;
+    SparseFn fn;
+    if (esz == 8)
+        fn = sp_pick_hu<double, 1>(has_h, unit, jac, trackd);
+    else if (esz == 4)
+        fn = vec == 4   ? sp_pick_hu<float, 4>(has_h, unit, jac, trackd)
+             : vec == 2 ? sp_pick_hu<float, 2>(has_h, unit, jac, trackd)
+                        : sp_pick_hu<float, 1>(has_h, unit, jac, trackd);
+    else
+        fn = vec == 4   ? sp_pick_hu<_Float16, 4>(has_h, unit, jac, trackd)
+             : vec == 2 ? sp_pick_hu<_Float16, 2>(has_h, unit, jac, trackd)
+                        : sp_pick_hu<_Float16, 1>(has_h, unit, jac, trackd);
+    const size_t rows = (size_t)a.nslot + 1;
+    const size_t lds = ((rows * rpw * esz * (jac ? 2 : 1) + 15) & ~(size_t)15) + rpw * RUN_AREA_BYTES;
+    const int nq = rpw / (esz == 8 ? 1 : vec);
+    if (Tq * nq > 1024 || Tq < 1)
+        return hipErrorInvalidConfiguration;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess)
+            return e;
+    }
+    dim3 grid((a.R + rpw - 1) / rpw), block(Tq * nq);
+    hipLaunchKernelGGL(fn, grid, block, lds, s, a, lg);
+    return hipGetLastError();
+}
+
+}  // namespace mars

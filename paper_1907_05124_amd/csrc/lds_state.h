@@ -1,0 +1,183 @@
+// Helpers of the LDS-resident solvers (lattice and sparse): storage types of
+// the magnetisation, the fp32 tanh, and reads/writes of VEC consecutive runs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "common_device.h"
+#include "mars_internal.h"
+
+namespace mars {
+
+template <typename S>
+struct LStore;
+template <>
+struct LStore<double> {
+    typedef double C;
+    __device__ static inline double ld(double v) { return v; }
+    __device__ static inline double st(double v) { return v; }
+};
+template <>
+struct LStore<float> {
+    typedef float C;
+    __device__ static inline float ld(float v) { return v; }
+    __device__ static inline float st(float v) { return v; }
+};
+template <>
+struct LStore<_Float16> {
+    typedef float C;
+    __device__ static inline float ld(_Float16 v) { return (float)v; }
+    __device__ static inline _Float16 st(float v) { return (_Float16)v; }
+};
+
+__device__ inline double l_tanh(double x) { return tanh(x); }
+// tanh(a) = 1 - 2 / (exp(2a) + 1) on |a| with the hardware exp2 and reciprocal,
+// sign restored afterwards (exactly odd); absolute error ~1e-7
+__device__ inline float l_tanh(float x)
+{
+    const float a = fabsf(x);
+    const float e = __builtin_amdgcn_exp2f(a * 2.8853900817779268f);
+    const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+    return copysignf(t, x);
+}
+__device__ inline double l_scale(double phi, double T, double invT) { return phi / T; }
+__device__ inline float l_scale(float phi, double T, float invT) { return phi * invT; }
+// Phi / T with the per-run factor of run_scale: a true division in fp64, a
+// multiply by the rounded inverse in fp32
+__device__ inline double l_apply(double phi, double T) { return phi / T; }
+__device__ inline float l_apply(float phi, float invT) { return phi * invT; }
+
+template <typename S, int VEC>
+struct Pack {
+    S v[VEC];
+};
+
+template <typename S, int VEC>
+__device__ inline Pack<S, VEC> lds_get(const S *p)
+{
+    Pack<S, VEC> r;
+    if constexpr (VEC == 4 && sizeof(S) == 4) {
+        const float4 f = *reinterpret_cast<const float4 *>(p);
+        r.v[0] = f.x;
+        r.v[1] = f.y;
+        r.v[2] = f.z;
+        r.v[3] = f.w;
+    } else if constexpr (VEC == 4 && sizeof(S) == 2) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p);
+        r.v[0] = __builtin_bit_cast(S, (unsigned short)(u.x & 0xffffu));
+        r.v[1] = __builtin_bit_cast(S, (unsigned short)(u.x >> 16));
+        r.v[2] = __builtin_bit_cast(S, (unsigned short)(u.y & 0xffffu));
+        r.v[3] = __builtin_bit_cast(S, (unsigned short)(u.y >> 16));
+    } else if constexpr (VEC == 2 && sizeof(S) == 2) {
+        const uint32_t u = *reinterpret_cast<const uint32_t *>(p);
+        r.v[0] = __builtin_bit_cast(S, (unsigned short)(u & 0xffffu));
+        r.v[1] = __builtin_bit_cast(S, (unsigned short)(u >> 16));
+    } else if constexpr (VEC == 2 && sizeof(S) == 4) {
+        const float2 f = *reinterpret_cast<const float2 *>(p);
+        r.v[0] = f.x;
+        r.v[1] = f.y;
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            r.v[e] = p[e];
+    }
+    return r;
+}
+
+template <typename S, int VEC>
+__device__ inline void lds_put(S *p, const Pack<S, VEC> &r)
+{
+    if constexpr (VEC == 4 && sizeof(S) == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    } else if constexpr (VEC == 4 && sizeof(S) == 2) {
+        auto b = [&](int e) { return (uint32_t)__builtin_bit_cast(unsigned short, r.v[e]); };
+        *reinterpret_cast<uint2 *>(p) = make_uint2(b(0) | (b(1) << 16), b(2) | (b(3) << 16));
+    } else if constexpr (VEC == 2 && sizeof(S) == 2) {
+        const uint32_t u = (uint32_t)__builtin_bit_cast(unsigned short, r.v[0]) |
+                           ((uint32_t)__builtin_bit_cast(unsigned short, r.v[1]) << 16);
+        *reinterpret_cast<uint32_t *>(p) = u;
+    } else if constexpr (VEC == 2 && sizeof(S) == 4) {
+        *reinterpret_cast<float2 *>(p) = make_float2(r.v[0], r.v[1]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+            p[e] = r.v[e];
+    }
+}
+
+// Level bookkeeping of one run, kept in LDS and advanced by one thread at the
+// end of each sweep: the run walks its own temperature levels (Algorithm 1),
+// one sweep per level or, with max_sweeps > 1, sweeps until the largest
+// change d falls below d_min.  The other threads only read T, invT and done.
+struct RunState {
+    LevelWalker lw;
+    double T;
+    float invT32;
+    int done;
+    int sw;       // sweeps at the current level
+    int sweeps, levels, caps;
+
+    __device__ void start(const RunSchedule &rs, double T0, bool live)
+    {
+        lw.start(rs, live ? T0 : 1.0);
+        done = (!live || lw.done) ? 1 : 0;
+        T = done ? 1.0 : lw.T;
+        invT32 = done ? 0.0f : (float)(1.0 / lw.T);
+        sw = sweeps = levels = caps = 0;
+    }
+    __device__ void advance(const RunSchedule &rs)
+    {
+        ++levels;
+        sw = 0;
+        lw.next(rs);
+        if (lw.done) {
+            done = 1;
+        } else {
+            T = lw.T;
+            invT32 = (float)(1.0 / lw.T);
+        }
+    }
+    // d: the run's largest change in the sweep (fp32 image), read only when
+    // several sweeps per level are allowed
+    __device__ void end_sweep(const RunSchedule &rs, float d, bool trackd, int max_sweeps, double d_min)
+    {
+        if (done)
+            return;
+        ++sweeps;
+        if (!trackd) {
+            advance(rs);
+            return;
+        }
+        ++sw;
+        const bool conv = (double)d < d_min;
+        if (conv || sw >= max_sweeps) {
+            if (!conv && max_sweeps > 1)
+                ++caps;
+            advance(rs);
+        }
+    }
+    __device__ void write_stats(int64_t *runstat, int run) const
+    {
+        runstat[(size_t)run * 4 + 0] = sweeps;
+        runstat[(size_t)run * 4 + 1] = levels;
+        runstat[(size_t)run * 4 + 2] = caps;
+        runstat[(size_t)run * 4 + 3] = 0;
+    }
+};
+
+// Per-run LDS area of an LDS-resident solver: state, then the sweep's
+// largest change (bit pattern of a non-negative float, for atomicMax).
+constexpr size_t RUN_AREA_BYTES = sizeof(RunState) + sizeof(uint32_t);
+static_assert(RUN_AREA_BYTES <= RUN_AREA_MAX, "per-run LDS area exceeds the launcher's reservation");
+
+template <typename C>
+__device__ inline C run_scale(const RunState &r);
+template <>
+__device__ inline float run_scale<float>(const RunState &r) { return r.invT32; }
+template <>
+__device__ inline double run_scale<double>(const RunState &r) { return r.T; }
+
+}  // namespace mars

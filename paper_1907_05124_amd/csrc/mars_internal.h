@@ -9,10 +9,14 @@
 #include <vector>
 
 #include "../../include/mars.h"
+#include "common_device.h"
 
 namespace mars {
 
 enum Kind { KIND_DENSE = 0, KIND_CSR = 1, KIND_LATTICE = 2 };
+
+constexpr int SELL_H = 8;  // slots per slice of the sparse solver's layout
+constexpr size_t RUN_AREA_MAX = 96;  // LDS bytes reserved per run for its level state
 
 // Device buffer owned by an instance; grows on demand, freed on destroy.
 struct DevBuf {
@@ -61,10 +65,23 @@ struct Instance {
     int32_t *rowptr = nullptr;
     uint32_t *colval = nullptr;   // (col << 8) | uint8(val)
     int ncolours = 0;
-    int32_t *phase_ptr = nullptr; // [ncolours+1]
-    int32_t *phase_vert = nullptr;// [N] vertices sorted by colour
     int maxdeg = 0;
-    std::vector<int32_t> h_phase_ptr;
+    // sliced-ELL copy used by the solver: vertices relabelled into slots,
+    // colour class by colour class, each class sorted by degree (descending)
+    // and padded to a multiple of SELL_H slots; slice s (SELL_H consecutive
+    // slots) holds width w_s = its largest degree and entries
+    // colsell[off_s + j * SELL_H + (slot % SELL_H)], j < w_s, each
+    // (neighbour slot) | (uint8(weight) << 24); a missing entry names the
+    // all-zero row nslot with weight +1
+    int nslot = 0;
+    bool unit = false;            // every |weight| == 1
+    int32_t *perm = nullptr;      // [nslot] slot -> vertex, -1 for padding
+    int32_t *sl_meta = nullptr;   // [2 x nslot / SELL_H] (off_s, w_s)
+    uint32_t *colsell = nullptr;
+    int32_t *cls = nullptr;       // [2 x ncolours] (first slot, vertex count)
+    std::vector<int32_t> h_cls;
+    float *hperm = nullptr;       // [nslot] h/2 by slot (fp32), 0 on padding
+    double *hperm64 = nullptr;    // [nslot] h/2 by slot (fp64)
     // lattice
     int dim = 0;
     int L[3] = {1, 1, 1};
@@ -144,5 +161,44 @@ struct GraphSolve {
     int64_t *runstat;      // [R x 4]
 };
 mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s);
+
+// kernel arguments of the lattice / sparse solvers
+struct GraphArgs {
+    int N;
+    // csr
+    const int32_t *rowptr;
+    const uint32_t *colval;
+    int nphase;
+    // sliced ELL (see Instance)
+    int nslot;
+    const int32_t *perm;
+    const int32_t *sl_meta;
+    const uint32_t *colsell;
+    const int32_t *cls;
+    // lattice
+    int dim, L0, L1, L2;
+    const uint8_t *bondbits;
+    // field
+    const float *hhalf32;
+    const double *hhalf64;
+    // schedule
+    RunSchedule rs;
+    int max_sweeps;
+    double d_min;
+    double damping;
+    // runs
+    uint64_t seed;
+    int R;
+    int rpw;
+    const void *m0;
+    const double *T0;
+    void *m_final;
+    int8_t *spins;
+    int64_t *runstat;
+};
+
+hipError_t launch_lattice_solve(const GraphArgs &a, int esz, int rpw, bool jac, bool trackd, hipStream_t s);
+hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, bool jac, bool trackd,
+                               bool unit, hipStream_t s);
 
 }  // namespace mars

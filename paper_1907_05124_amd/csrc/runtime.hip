@@ -84,8 +84,9 @@ static void destroy_instance(Instance *I)
         (void)hipEventSynchronize(I->done_event);
         (void)hipEventDestroy(I->done_event);
     }
-    void *ptrs[] = {I->J, I->Jbf, I->Jfix, I->Jlimb, I->hhalf, I->hhalf64, I->hfix, I->rowptr,
-                    I->colval, I->phase_ptr, I->phase_vert, I->bondbits};
+    void *ptrs[] = {I->J,      I->Jbf,     I->Jfix,    I->Jlimb,   I->hhalf, I->hhalf64,
+                    I->hfix,   I->rowptr,  I->colval,  I->perm,    I->sl_meta, I->colsell,
+                    I->cls,    I->hperm,   I->hperm64, I->bondbits};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -361,23 +362,104 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
             pvert[fill[colour[v]]++] = v;
     }
     I->ncolours = ncol;
-    I->h_phase_ptr = pptr;
+    // CSR copy for exact energies (original labels)
     std::vector<uint32_t> cv((size_t)std::max<long long>(nnz, 1));
     for (long long k = 0; k < nnz; ++k)
         cv[k] = ((uint32_t)col[k] << 8) | (uint32_t)(uint8_t)val[k];
+    // sliced-ELL copy for the solver: classes in colour order, each sorted by
+    // degree (descending, ties by index) and padded to whole slices, so that
+    // the SELL_H vertices of a slice have similar degrees and the threads of a
+    // wave read consecutive entries
+    std::vector<int32_t> perm, slot_of((size_t)N), cls((size_t)2 * ncol);
+    for (int c = 0; c < ncol; ++c) {
+        std::vector<int32_t> vs(pvert.begin() + pptr[c], pvert.begin() + pptr[c + 1]);
+        std::stable_sort(vs.begin(), vs.end(), [&](int32_t x, int32_t y) {
+            return rowptr[x + 1] - rowptr[x] > rowptr[y + 1] - rowptr[y];
+        });
+        cls[2 * c] = (int32_t)perm.size();
+        cls[2 * c + 1] = (int32_t)vs.size();
+        for (int32_t v : vs) {
+            slot_of[v] = (int32_t)perm.size();
+            perm.push_back(v);
+        }
+        while (perm.size() % SELL_H)
+            perm.push_back(-1);
+    }
+    const int nslot = (int)perm.size();
+    if (nslot >= (1 << 24))
+        return set_error(MARS_E_UNSUPPORTED, "sparse instances are limited to fewer than 2^24 slots");
+    const int nslice = nslot / SELL_H;
+    std::vector<int32_t> meta((size_t)2 * nslice);
+    size_t total = 0;
+    for (int sl = 0; sl < nslice; ++sl) {
+        int w = 0;
+        for (int l = 0; l < SELL_H; ++l) {
+            const int v = perm[(size_t)sl * SELL_H + l];
+            if (v >= 0)
+                w = std::max(w, rowptr[v + 1] - rowptr[v]);
+        }
+        meta[2 * sl] = (int32_t)total;
+        meta[2 * sl + 1] = w;
+        total += (size_t)w * SELL_H;
+    }
+    if (total >= (size_t)1 << 31)
+        return set_error(MARS_E_UNSUPPORTED, "sliced layout exceeds 2^31 entries");
+    std::vector<uint32_t> cs(std::max<size_t>(total, 1), (uint32_t)nslot | (1u << 24));
+    bool unit = true;
+    for (int sl = 0; sl < nslice; ++sl)
+        for (int l = 0; l < SELL_H; ++l) {
+            const int v = perm[(size_t)sl * SELL_H + l];
+            if (v < 0)
+                continue;
+            for (int k = rowptr[v]; k < rowptr[v + 1]; ++k) {
+                const size_t at = (size_t)meta[2 * sl] + (size_t)(k - rowptr[v]) * SELL_H + l;
+                cs[at] = (uint32_t)slot_of[col[k]] | ((uint32_t)(uint8_t)val[k] << 24);
+                unit &= (val[k] == 1 || val[k] == -1);
+            }
+        }
+    I->nslot = nslot;
+    I->unit = unit;
+    I->h_cls = cls;
     if ((st = dev_alloc(&I->rowptr, (size_t)N + 1)) != MARS_OK)
         return st;
     if ((st = dev_alloc(&I->colval, cv.size())) != MARS_OK)
         return st;
-    if ((st = dev_alloc(&I->phase_ptr, pptr.size())) != MARS_OK)
+    if ((st = dev_alloc(&I->perm, perm.size())) != MARS_OK)
         return st;
-    if ((st = dev_alloc(&I->phase_vert, (size_t)N)) != MARS_OK)
+    if ((st = dev_alloc(&I->sl_meta, meta.size())) != MARS_OK)
+        return st;
+    if ((st = dev_alloc(&I->colsell, cs.size())) != MARS_OK)
+        return st;
+    if ((st = dev_alloc(&I->cls, cls.size())) != MARS_OK)
         return st;
     hipStream_t s = I->own_stream;
     MARS_HIP(hipMemcpyAsync(I->rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s));
     MARS_HIP(hipMemcpyAsync(I->colval, cv.data(), sizeof(uint32_t) * cv.size(), hipMemcpyHostToDevice, s));
-    MARS_HIP(hipMemcpyAsync(I->phase_ptr, pptr.data(), sizeof(int32_t) * pptr.size(), hipMemcpyHostToDevice, s));
-    MARS_HIP(hipMemcpyAsync(I->phase_vert, pvert.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
+    MARS_HIP(hipMemcpyAsync(I->perm, perm.data(), sizeof(int32_t) * perm.size(), hipMemcpyHostToDevice, s));
+    MARS_HIP(hipMemcpyAsync(I->sl_meta, meta.data(), sizeof(int32_t) * meta.size(), hipMemcpyHostToDevice, s));
+    MARS_HIP(hipMemcpyAsync(I->colsell, cs.data(), sizeof(uint32_t) * cs.size(), hipMemcpyHostToDevice, s));
+    MARS_HIP(hipMemcpyAsync(I->cls, cls.data(), sizeof(int32_t) * cls.size(), hipMemcpyHostToDevice, s));
+    if (h) {
+        bool any = false;
+        for (int i = 0; i < N; ++i)
+            any |= h[i] != 0.0f;
+        if (any) {
+            std::vector<float> hp((size_t)nslot, 0.0f);
+            std::vector<double> hp64((size_t)nslot, 0.0);
+            for (int sl = 0; sl < nslot; ++sl)
+                if (perm[sl] >= 0) {
+                    hp[sl] = h[perm[sl]] * 0.5f;
+                    hp64[sl] = (double)h[perm[sl]] * 0.5;
+                }
+            if ((st = dev_alloc(&I->hperm, (size_t)nslot)) != MARS_OK)
+                return st;
+            if ((st = dev_alloc(&I->hperm64, (size_t)nslot)) != MARS_OK)
+                return st;
+            MARS_HIP(hipMemcpyAsync(I->hperm, hp.data(), sizeof(float) * nslot, hipMemcpyHostToDevice, s));
+            MARS_HIP(hipMemcpyAsync(I->hperm64, hp64.data(), sizeof(double) * nslot, hipMemcpyHostToDevice, s));
+            MARS_HIP(hipStreamSynchronize(s));
+        }
+    }
     MARS_HIP(hipStreamSynchronize(s));
     return upload_h(I, h, N);
 }

@@ -60,6 +60,82 @@ def test_one_level_parity(case, precision, tol):
     assert err <= tol, err
 
 
+RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "ea3d_8", "ea2d_6x4", "lat_field"]
+
+
+@pytest.mark.parametrize("case", RUN_BLOCK_CASES)
+@pytest.mark.parametrize("R,vec", [(1031, ""), (2053, "1"), (4100, ""), (4100, "4"), (16400, "")])
+def test_one_level_run_blocks(case, R, vec, monkeypatch):
+    """Several runs per workgroup (R >= 1024) and per thread, with a ragged
+    last block: one fp32 level within 1e-5 of the oracle.  MARS_SPARSE_VEC
+    forces 1 or 4 runs per thread on the sparse path."""
+    M = _mars()
+    if vec:
+        monkeypatch.setenv("MARS_SPARSE_VEC", vec)
+    else:
+        monkeypatch.delenv("MARS_SPARSE_VEC", raising=False)
+    inst = CASES[case]()
+    sch = _rel_sched(inst, precision="fp32", level_count=1)
+    announce("graph run blocks", case, R, vec)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 29, want_m=True)
+    ref = O.solve(inst, R, sch, 29, run_count=R)
+    err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("case", ["er_field", "er_unit", "lat_field", "ea3d_8"])
+@pytest.mark.parametrize("R", [200, 1031, 4100])
+@pytest.mark.parametrize("precision,levels,tol", [("fp32", 1, 1e-5), ("fp64", 4, 1e-9)])
+def test_jacobi_parity(case, R, precision, levels, tol):
+    """Synchronous updates (both state copies, swapped after each sweep)."""
+    M = _mars()
+    inst = CASES[case]()
+    sch = _rel_sched(inst, precision=precision, update="jacobi", level_count=levels)
+    announce("graph jacobi", case, R, precision, levels)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 37, want_m=True)
+    ref = O.solve(inst, R, sch, 37, run_count=R)
+    err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
+    assert err <= tol, err
+
+
+def _dense_couplings(inst):
+    if isinstance(inst, I.LatticeInstance):
+        return I.lattice_dense(inst).J.astype(np.float64)
+    return I.csr_dense(inst).J.astype(np.float64)
+
+
+@pytest.mark.parametrize("case", ["er_pm1", "er_field", "ea3d_8", "lat_field"])
+@pytest.mark.parametrize("R", [200, 1031, 4100])
+def test_one_level_fp16_storage(case, R):
+    """fp16 magnetisation storage, fp32 fields, one level from fp16-exact
+    initial states (the same for the oracle).  A spin's new value differs from
+    the oracle's by its fp16 rounding (<= 2^-12 for |m| < 1) plus fp32
+    arithmetic, and by what it inherits from the phases before its own: a
+    neighbour off by e_j moves Phi_i by |J_ij| e_j and m_i by at most
+    (1 - m_i^2) / T times that (first order, with 10 % slack); the bound is
+    accumulated phase by phase."""
+    M = _mars()
+    torch = require_gpu()
+    inst = CASES[case]()
+    sch = _rel_sched(inst, precision="fp16", level_count=1)
+    m0 = O.initial_m(31, R, inst.N).astype(np.float16).astype(np.float32)
+    announce("graph fp16 one level", case, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 31, m0=torch.from_numpy(m0).cuda(), want_m=True)
+    ref = O.solve(inst, R, sch.replace(precision="fp64"), 31, run_count=R, m0=m0.astype(np.float64))
+    ph, _ = O.phases(inst, sch)
+    Ja = np.abs(_dense_couplings(inst))
+    gain = (1.0 - ref["m"] ** 2) / ref["T0"][None, :]
+    tol = np.zeros_like(ref["m"])
+    for c in np.unique(ph):
+        own, earlier = ph == c, ph < c
+        tol[own] = 2.0**-12 + 1e-5 + 1.1 * gain[own] * (Ja[np.ix_(own, earlier)] @ tol[earlier])
+    err = np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"])
+    assert np.all(err <= tol), float(np.max(err / tol))
+
+
 @pytest.mark.parametrize("case", ["ea2d_16", "ea3d_8", "er_pm1", "lat_field"])
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-9)])
 def test_anneal_parity(case, precision, tol):
@@ -152,15 +228,16 @@ def test_jacobi_sublattice_symmetry_gpu():
             assert np.array_equal(b["m"].cpu().numpy(), ((-1.0) ** k) * D[:, None] * a["m"].cpu().numpy())
 
 
-def test_paper_schedule_graph():
+@pytest.mark.parametrize("R", [64, 1024])
+def test_paper_schedule_graph(R):
     """Linear scheduler with d < d_min = 1e-4 on a sparse graph: identical level
-    counts, near-identical sweep totals and final states."""
+    counts, near-identical sweep totals and final states (R = 1024 puts two
+    runs in each workgroup and thread)."""
     M = _mars()
     inst = I.er_instance(400, 10, p=0.03, weights="pm1")
     s = I.field_scale(inst)
     sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=2.0 * s, c_step=0.2 * s, max_sweeps=400, d_min=1e-4)
-    R = 64
-    announce("graph paper schedule")
+    announce("graph paper schedule", R)
     with M.Instance.from_inputs(inst) as g:
         out = g.solve_ex(R, sch, 41, want_m=True)
     ref = O.solve(inst, R, sch, 41, run_count=R)
