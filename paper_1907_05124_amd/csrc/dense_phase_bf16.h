@@ -25,8 +25,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short ushortx8 __attribute__((ext_vector_type(8)));
 
-constexpr int HBK = 64;        // slab depth (elements)
-constexpr int HLD = HBK + 8;   // padded LDS row (elements)
+constexpr int HBK = 64;        // default slab depth (elements)
 
 __device__ inline float bf16_to_float(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -48,7 +47,7 @@ __device__ inline float bf16_form_tanh(float x)
     return copysignf(t, x);
 }
 
-template <int BM, int BN, int WM, int WN, int PF>
+template <int BM, int BN, int WM, int WN, int PF, int BK = HBK, bool BLEND = true>
 __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
     const unsigned short *__restrict__ J, int ldj, const unsigned short *__restrict__ Mold,
     unsigned short *__restrict__ Mnew, int ldk, int R, int p0, int p1, int nrt, int nct, int kpad,
@@ -57,13 +56,15 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
     constexpr int NT = 64 * WM * WN;
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int MB = TM / 32, NB = TN / 32;
-    constexpr int CA = BM * HBK / 8, CB = BN * HBK / 8;  // 16-byte chunks per slab
+    constexpr int CA = BM * BK / 8, CB = BN * BK / 8;  // 16-byte chunks per slab
+    constexpr int CR = BK / 8;                         // chunks per slab row
+    constexpr int LDR = BK + 8;                        // padded LDS row (elements)
     constexpr int LA = (CA + NT - 1) / NT, LB = (CB + NT - 1) / NT;
     static_assert(MB >= 1 && NB >= 1, "tile shape");
     static_assert(PF >= 1 && PF <= 4, "prefetch ring");
 
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][BM][HLD];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN][HLD];
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][BM][LDR];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN][LDR];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -89,15 +90,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
                 acc[a][b][v] = 0.0f;
 
     ushortx8 ga[PF][LA], gb[PF][LB];
-    // A chunk: run row, 8 spins; spins below p0 from the new buffer, a chunk
-    // straddling p0 is blended element by element
+    // A chunk: run row, 8 spins; spins below p0 from the new buffer.  Both
+    // forms are branch-free, so that the loads of a slab stay in flight
+    // while the previous slab is multiplied: with p0 a multiple of 8 no chunk
+    // straddles p0 and the chunk's buffer is selected; otherwise (BLEND) both
+    // buffers are read and blended element by element.
     auto load_a = [&](ushortx8 &dst, int c, int k0) {
-        const int row = c >> 3, kc = k0 + (c & 7) * 8;
+        const int row = c / CR, kc = k0 + (c % CR) * 8;
         const size_t off = (size_t)(r0 + row) * ldk + kc;
-        if (kc + 8 <= p0) {
-            dst = *reinterpret_cast<const ushortx8 *>(Mnew + off);
-        } else if (kc >= p0) {
-            dst = *reinterpret_cast<const ushortx8 *>(Mold + off);
+        if constexpr (!BLEND) {
+            dst = *reinterpret_cast<const ushortx8 *>((kc < p0 ? Mnew : Mold) + off);
         } else {
             const ushortx8 x = *reinterpret_cast<const ushortx8 *>(Mnew + off);
             const ushortx8 y = *reinterpret_cast<const ushortx8 *>(Mold + off);
@@ -117,46 +119,47 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
     {                                                                                               \
         const int c_ = tid + q * NT;                                                                \
         if (c_ < CB)                                                                                \
-            (RB)[q] = *reinterpret_cast<const ushortx8 *>(J + (size_t)(i0 + (c_ >> 3)) * ldj + (k0) + (c_ & 7) * 8); \
+            (RB)[q] = *reinterpret_cast<const ushortx8 *>(J + (size_t)(i0 + c_ / CR) * ldj + (k0) + (c_ % CR) * 8); \
     }
 #define H_STORE(RA, RB, buf)                                                                        \
     _Pragma("unroll") for (int q = 0; q < LA; ++q)                                                  \
     {                                                                                               \
         const int c_ = tid + q * NT;                                                                \
         if (c_ < CA)                                                                                \
-            *reinterpret_cast<ushortx8 *>(&As[(buf)][c_ >> 3][(c_ & 7) * 8]) = (RA)[q];             \
+            *reinterpret_cast<ushortx8 *>(&As[(buf)][c_ / CR][(c_ % CR) * 8]) = (RA)[q];            \
     }                                                                                               \
     _Pragma("unroll") for (int q = 0; q < LB; ++q)                                                  \
     {                                                                                               \
         const int c_ = tid + q * NT;                                                                \
         if (c_ < CB)                                                                                \
-            *reinterpret_cast<ushortx8 *>(&Bs[(buf)][c_ >> 3][(c_ & 7) * 8]) = (RB)[q];             \
+            *reinterpret_cast<ushortx8 *>(&Bs[(buf)][c_ / CR][(c_ % CR) * 8]) = (RB)[q];            \
     }
 
     // Slabs move global -> registers -> LDS.  Registers hold a ring of PF
     // slabs: at step kt the ring slot of slab kt (already in LDS) is refilled
     // with slab kt + PF, the step computes on slab kt, then slab kt + 1 goes
     // from its ring slot into the other LDS buffer.  A load thus has PF
-    // compute steps to arrive.
-    const int nk = kpad / HBK;
+    // compute steps to arrive.  The refill is unconditional (past the last
+    // slab it re-reads the last one) so that the wait before each LDS store
+    // covers only the older loads and the younger ones stay in flight.
+    const int nk = kpad / BK;
 #pragma unroll
-    for (int s = 0; s < PF; ++s)
-        if (s < nk) {
-            H_LOAD(ga[s], gb[s], s * HBK);
-        }
+    for (int s = 0; s < PF; ++s) {
+        const int kl = s < nk ? s : nk - 1;
+        H_LOAD(ga[s], gb[s], kl * BK);
+    }
     H_STORE(ga[0], gb[0], 0);
     __syncthreads();
     for (int kb = 0; kb < nk; kb += PF) {
 #pragma unroll
         for (int s = 0; s < PF; ++s) {
             const int kt = kb + s;
+            const int kl = kt + PF < nk ? kt + PF : nk - 1;
+            H_LOAD(ga[s], gb[s], kl * BK);
             if (kt < nk) {
                 const int cur = kt & 1;
-                if (kt + PF < nk) {
-                    H_LOAD(ga[s], gb[s], (kt + PF) * HBK);
-                }
 #pragma unroll
-                for (int ks = 0; ks < HBK / 16; ++ks) {
+                for (int ks = 0; ks < BK / 16; ++ks) {
                     bf16x8 fa[MB], fb[NB];
 #pragma unroll
                     for (int a = 0; a < MB; ++a)
@@ -181,34 +184,49 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
 #undef H_STORE
 
     // epilogue: element (run = row, spin = column) of each 32 x 32 block; lane
-    // l holds spin column l%32, register v holds run row 8*(v/4) + 4*(l/32) + v%4
+    // l holds spin column l%32, register v holds run row 8*(v/4) + 4*(l/32) + v%4.
+    // Every operand of the update is loaded first, unconditionally (rows
+    // below the padded run count and columns below the padded dimension are
+    // in bounds), so the loads overlap instead of one round trip per element.
     const bool damp = gamma != 1.0f;
+    float itv[MB][16], hv[NB];
+    unsigned short ov[MB][NB][16];
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int run = r0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+            itv[a][v] = invT[run];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                ov[a][b][v] = Mold[(size_t)run * ldk + i0 + wn * TN + b * 32 + li];
+        }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        hv[b] = hhalf ? hhalf[i0 + wn * TN + b * 32 + li] : 0.0f;
+    // The stores are unconditional too (a conditional store would make the
+    // wait counts conservative again): a row past R writes its old value
+    // back; a column past p1 belongs to a later phase of this sweep, which
+    // overwrites it before anything reads it (columns past N compute 0 from
+    // the zero padding of J and h).
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int run = r0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
             const bool rok = run < R;
-            const float it = rok ? invT[run] : -1.0f;
+            const float it = rok ? itv[a][v] : -1.0f;  // < 0: frozen (finished run or padding row)
             float dl = 0.0f;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int spin = i0 + wn * TN + b * 32 + li;
-                if (rok && spin < p1) {
-                    const size_t off = (size_t)run * ldk + spin;
-                    const float old = bf16_to_float(Mold[off]);
-                    float nw = old;
-                    if (it >= 0.0f) {
-                        float phi = acc[a][b][v];
-                        if (hhalf)
-                            phi += hhalf[spin];
-                        const float th = bf16_form_tanh(phi * it);
-                        nw = damp ? (1.0f - gamma) * old + gamma * th : th;
-                    }
-                    const unsigned short nb16 = float_to_bf16(nw);
-                    Mnew[off] = nb16;
-                    dl = fmaxf(dl, fabsf(bf16_to_float(nb16) - old));
-                }
+                const float old = bf16_to_float(ov[a][b][v]);
+                const float th = bf16_form_tanh((acc[a][b][v] + hv[b]) * it);
+                const float upd = damp ? (1.0f - gamma) * old + gamma * th : th;
+                const unsigned short nb16 = it >= 0.0f ? float_to_bf16(upd) : ov[a][b][v];
+                Mnew[(size_t)run * ldk + spin] = nb16;
+                const float dd = fabsf(bf16_to_float(nb16) - old);
+                dl = (rok && spin < p1) ? fmaxf(dl, dd) : dl;
             }
             if (dmax) {
                 // per-run maximum over the 32 spin lanes of this half-wave

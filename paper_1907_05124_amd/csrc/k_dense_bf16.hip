@@ -1,14 +1,44 @@
 // BF16 form of the dense path: conversion of J, state initialisation in the
 // run-major bf16 layout, the phase launcher, and rounding into the padded
 // spin operand shared with the fp32 form (exact energies are unchanged).
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "common_device.h"
 #include "dense_phase_bf16.h"
 #include "mars_internal.h"
 
 namespace mars {
 
-// Tile shape measured fastest on the SK N=2000 x 4096-run phase shape.
-constexpr int HBM_ = 128, HBN_ = 128, HWM = 4, HWN = 4, HPF = 1;
+// Tile variants of the phase kernel.  Every variant reduces each output
+// element over K in the same order (64-deep slabs, one wave per 32 x 32
+// block), so all of them produce bitwise identical results; they differ in
+// how many workgroups a phase yields.  128 x 128 x 16 waves is the fastest on
+// the SK N=2000 x 4096-run shape; smaller tiles fill the GPU on small
+// instances.
+typedef void (*Bf16PhaseFn)(const unsigned short *, int, const unsigned short *, unsigned short *, int, int, int,
+                            int, int, int, int, const float *, const float *, float, uint32_t *);
+// fn_aligned: the phase starts at a multiple of 8 spins (no 8-spin chunk
+// straddles it); fn_blend: any start.
+struct Bf16Variant {
+    int bm, bn, threads;
+    Bf16PhaseFn fn_aligned, fn_blend;
+};
+#define BF16_VARIANT(BM, BN, WM, WN, PF)                                                          \
+    {                                                                                           \
+        BM, BN, 64 * WM * WN, k_dense_phase_bf16<BM, BN, WM, WN, PF, HBK, false>,              \
+            k_dense_phase_bf16<BM, BN, WM, WN, PF, HBK, true>                                   \
+    }
+static const Bf16Variant kBf16Variants[] = {
+    BF16_VARIANT(128, 128, 4, 4, 1),
+    BF16_VARIANT(64, 128, 2, 4, 1),
+    BF16_VARIANT(128, 64, 4, 2, 1),
+    BF16_VARIANT(64, 64, 2, 2, 1),
+};
+#undef BF16_VARIANT
+constexpr int kNumBf16Variants = sizeof(kBf16Variants) / sizeof(kBf16Variants[0]);
 
 __global__ void k_bf16_from_f32(const float *J, size_t n, unsigned short *Jb)
 {
@@ -52,13 +82,69 @@ void launch_bf16_init_state(uint64_t seed, int N, int R, int ldk, const float *m
 }
 
 void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R,
-                             int p0, int p1, const float *invT, float gamma, uint32_t *dmax, hipStream_t s)
+                             int p0, int p1, const float *invT, float gamma, uint32_t *dmax, int variant,
+                             hipStream_t s)
 {
-    const int nrt = (R + HBM_ - 1) / HBM_;
-    const int nct = (p1 - p0 + HBN_ - 1) / HBN_;
+    const Bf16Variant &v = kBf16Variants[(variant >= 0 && variant < kNumBf16Variants) ? variant : 0];
+    const int nrt = (R + v.bm - 1) / v.bm;
+    const int nct = (p1 - p0 + v.bn - 1) / v.bn;
     const int kpad = (I.N + HBK - 1) / HBK * HBK;
-    k_dense_phase_bf16<HBM_, HBN_, HWM, HWN, HPF><<<nrt * nct, 64 * HWM * HWN, 0, s>>>(
-        I.Jbf, I.Np, Mold, Mnew, ldk, R, p0, p1, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma, dmax);
+    hipLaunchKernelGGL((p0 % 8 == 0) ? v.fn_aligned : v.fn_blend, dim3(nrt * nct), dim3(v.threads), 0, s, I.Jbf,
+                       I.Np, Mold, Mnew, ldk, R, p0, p1, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma,
+                       dmax);
+}
+
+// Autotuner: the first solve of a (runs, phase width, N) shape times every
+// variant on its first phase (the phase is idempotent: it reads the previous
+// state and writes its own rows), with events on the solve's stream, and
+// keeps the fastest for the process.  MARS_BF16_TILE=<index> forces a variant.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, int> g_tune_cache;
+
+int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R, int p0,
+                       int p1, const float *invT, float gamma, hipStream_t s)
+{
+    if (const char *f = std::getenv("MARS_BF16_TILE")) {
+        const int v = std::atoi(f);
+        if (v >= 0 && v < kNumBf16Variants)
+            return v;
+    }
+    const auto key = std::make_tuple(R, p1 - p0, I.N);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end())
+            return it->second;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = 0;
+    float best_ms = 0.0f;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+    for (int v = 0; ok && v < kNumBf16Variants; ++v) {
+        launch_dense_phase_bf16(I, Mold, Mnew, ldk, R, p0, p1, invT, gamma, nullptr, v, s);  // warm
+        ok = hipEventRecord(e0, s) == hipSuccess;
+        for (int r = 0; ok && r < 3; ++r)
+            launch_dense_phase_bf16(I, Mold, Mnew, ldk, R, p0, p1, invT, gamma, nullptr, v, s);
+        ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
+             hipEventSynchronize(e1) == hipSuccess;
+        float ms = 0.0f;
+        ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (ok && (v == 0 || ms < best_ms)) {
+            best = v;
+            best_ms = ms;
+        }
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (!ok) {
+        (void)hipGetLastError();  // clear a failed timing; the default variant is used
+        return 0;
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = best;
+    return best;
 }
 
 // s = +1 if m >= 0 else -1 into the padded operand [ldr x Ke]; optional

@@ -119,13 +119,15 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
             const uint32_t b = bonds[v];
             C phi[VEC];
             if constexpr (sizeof(S) == 2 && VEC == 2) {
-                // packed pair of fp16 runs: one 32-bit read per neighbour, the
-                // bond's sign applied to both halves with one xor
+                // packed pair of fp16 runs: one 32-bit read per neighbour; each
+                // term is one mixed-precision fma of the stored half with the
+                // bond's +-1.0f (exact product, one rounding: the same value as
+                // converting and adding)
                 auto rd = [&](uint32_t o) -> uint32_t {
                     return *reinterpret_cast<const uint32_t *>(mb + (uint32_t)(vb + o));
                 };
-                auto sgn = [&](int k) -> uint32_t {
-                    return (uint32_t)__builtin_amdgcn_sbfe((int)b, k, 1) & 0x80008000u;
+                auto sgn = [&](int k) -> float {
+                    return __uint_as_float(((uint32_t)__builtin_amdgcn_sbfe((int)b, k, 1) & 0x80000000u) | 0x3f800000u);
                 };
                 auto lo = [](uint32_t u) -> float {
                     return (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xffffu));
@@ -133,21 +135,22 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
                 auto hi = [](uint32_t u) -> float {
                     return (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
                 };
-                const uint32_t u0 = rd(oxp) ^ sgn(0), u1 = rd(oxm) ^ sgn(1);
-                const uint32_t u2 = rd(oyp) ^ sgn(2), u3 = rd(oym) ^ sgn(3);
-                float p0 = lo(u0), p1 = hi(u0);
-                p0 += lo(u1);
-                p1 += hi(u1);
-                p0 += lo(u2);
-                p1 += hi(u2);
-                p0 += lo(u3);
-                p1 += hi(u3);
+                const uint32_t u0 = rd(oxp), u1 = rd(oxm), u2 = rd(oyp), u3 = rd(oym);
+                const float s0 = sgn(0), s1 = sgn(1), s2 = sgn(2), s3 = sgn(3);
+                float p0 = lo(u0) * s0, p1 = hi(u0) * s0;
+                p0 = __builtin_fmaf(lo(u1), s1, p0);
+                p1 = __builtin_fmaf(hi(u1), s1, p1);
+                p0 = __builtin_fmaf(lo(u2), s2, p0);
+                p1 = __builtin_fmaf(hi(u2), s2, p1);
+                p0 = __builtin_fmaf(lo(u3), s3, p0);
+                p1 = __builtin_fmaf(hi(u3), s3, p1);
                 if (DIM == 3) {
-                    const uint32_t u4 = rd(ozp) ^ sgn(4), u5 = rd(ozm) ^ sgn(5);
-                    p0 += lo(u4);
-                    p1 += hi(u4);
-                    p0 += lo(u5);
-                    p1 += hi(u5);
+                    const uint32_t u4 = rd(ozp), u5 = rd(ozm);
+                    const float s4 = sgn(4), s5 = sgn(5);
+                    p0 = __builtin_fmaf(lo(u4), s4, p0);
+                    p1 = __builtin_fmaf(hi(u4), s4, p1);
+                    p0 = __builtin_fmaf(lo(u5), s5, p0);
+                    p1 = __builtin_fmaf(hi(u5), s5, p1);
                 }
                 phi[0] = p0;
                 phi[1] = p1;

@@ -144,7 +144,10 @@ mars_status ensure_bf16_couplings(Instance &I, hipStream_t s);
 int bf16_state_rows(int R);
 void launch_bf16_init_state(uint64_t seed, int N, int R, int ldk, const float *m0, unsigned short *MT, hipStream_t s);
 void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R,
-                             int p0, int p1, const float *invT, float gamma, uint32_t *dmax, hipStream_t s);
+                             int p0, int p1, const float *invT, float gamma, uint32_t *dmax, int variant,
+                             hipStream_t s);
+int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R, int p0,
+                       int p1, const float *invT, float gamma, hipStream_t s);
 void launch_bf16_round(const unsigned short *MT, int ldk, int N, int R, int Ke, int8_t *spad, int8_t *spins,
                        float *m_final, hipStream_t s);
 

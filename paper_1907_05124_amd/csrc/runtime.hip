@@ -642,13 +642,19 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
         pb[b] = (int)((long long)b * N / B);
     const float gamma = (float)sc.damping;
     void *cur = w.Ma.p, *nxt = w.Mb.p;
+    // bf16 tile variant: the autotuner's choice for this shape (timed on the
+    // first phase at the first level, which the sweep then recomputes)
+    int variant = 0;
+    if (bf16 && kmax > 0)
+        variant = bf16_phase_variant(*I, (const unsigned short *)cur, (unsigned short *)nxt, I->Np, R, pb[0], pb[1],
+                                     table, gamma, s);
     auto sweep = [&](const float *invT, uint32_t *dmax) {
         for (int b = 0; b < B; ++b) {
             if (pb[b + 1] <= pb[b])
                 continue;
             if (bf16)
                 launch_dense_phase_bf16(*I, (const unsigned short *)cur, (unsigned short *)nxt, I->Np, R, pb[b],
-                                        pb[b + 1], invT, gamma, dmax, s);
+                                        pb[b + 1], invT, gamma, dmax, variant, s);
             else
                 launch_dense_phase_f32(*I, (const float *)cur, (float *)nxt, ldm, R, pb[b], pb[b + 1], invT, gamma,
                                        dmax, s);

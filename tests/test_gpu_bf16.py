@@ -69,6 +69,33 @@ def test_bf16_one_level(N, R, phases, field):
     assert np.all(err <= tol), float(np.max(err / tol))
 
 
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])
+def test_bf16_tile_variants_bitwise(tile, monkeypatch):
+    """The autotuner may pick any tile variant: every variant reduces each
+    element over K in the same order, so a 20-level anneal with a forced
+    variant equals the tuner's choice bit for bit (ragged runs and phase
+    widths, nonzero field)."""
+    M = _mars()
+    inst = I.sk_instance(517, 4, field_scale=0.3)
+    sch = _sched(inst, steps=20, phases=3)
+    announce("bf16 tile variant", tile)
+    monkeypatch.delenv("MARS_BF16_TILE", raising=False)
+    with M.Instance.from_inputs(inst) as g:
+        a = g.solve_ex(300, sch, 3, want_m=True, want_spins=True)
+        monkeypatch.setenv("MARS_BF16_TILE", tile)
+        b = g.solve_ex(300, sch, 3, want_m=True, want_spins=True)
+    assert np.array_equal(a["m"].cpu().numpy(), b["m"].cpu().numpy())
+    assert np.array_equal(a["spins"].cpu().numpy(), b["spins"].cpu().numpy())
+    assert np.array_equal(a["energies"].cpu().numpy(), b["energies"].cpu().numpy())
+
+
+@pytest.mark.parametrize("tile", ["1", "3"])
+def test_bf16_one_level_small_tiles(tile, monkeypatch):
+    """One level on a forced small-tile variant, same bar as the default tile."""
+    monkeypatch.setenv("MARS_BF16_TILE", tile)
+    test_bf16_one_level(517, 129, 3, 0.4)
+
+
 def test_bf16_anneal_quality_vs_fp32_and_oracle():
     """Whole anneal: the bf16 form's best-energy gap to the FP64 oracle (same
     seeds) is no worse than the fp32 form's by more than 0.2 % of |E|, and its
