@@ -150,31 +150,46 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
 
     // Epilogue (Algorithm 1 with the interface's sign: m = tanh(Phi / T)).
     // 32x32 MFMA result layout: lane l holds column l%32; register v holds row
-    // 8*(v/4) + 4*(l/32) + v%4 of the 32 x 32 block.
+    // 8*(v/4) + 4*(l/32) + v%4 of the 32 x 32 block.  The operands (1/T per
+    // run, old state, h/2) are loaded first and unconditionally (the tile's
+    // rows and columns lie inside the padded buffers), so that the loads
+    // overlap instead of one round trip per element.
     const bool damp = gamma != 1.0f;
+    float itv[NB], ov[NB][MB][16], hv[MB][16];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int col = c0 + wn * TN + b * 32 + li;
+        itv[b] = invT[col];
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                ov[b][a][v] = Mold[(size_t)(i0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * ka + (v & 3)) * ldm + col];
+    }
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            hv[a][v] = hhalf ? hhalf[i0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * ka + (v & 3)] : 0.0f;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int col = c0 + wn * TN + b * 32 + li;
         float dl = 0.0f;
         if (col < R) {
-            const float it = invT[col];
+            const float it = itv[b];
 #pragma unroll
             for (int a = 0; a < MB; ++a) {
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const int row = i0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * ka + (v & 3);
                     if (row >= p0 && row < p1) {
-                        const size_t off = (size_t)row * ldm + col;
-                        const float old = Mold[off];
+                        const float old = ov[b][a][v];
                         float nw = old;
                         if (it >= 0.0f) {
-                            float phi = acc[a][b][v];
-                            if (hhalf)
-                                phi += hhalf[row];
-                            const float th = tanhf(phi * it);
+                            const float th = tanhf((acc[a][b][v] + hv[a][v]) * it);
                             nw = damp ? (1.0f - gamma) * old + gamma * th : th;
                         }
-                        Mnew[off] = nw;
+                        Mnew[(size_t)row * ldm + col] = nw;
                         dl = fmaxf(dl, fabsf(nw - old));
                     }
                 }
