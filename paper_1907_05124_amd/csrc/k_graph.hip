@@ -7,9 +7,32 @@
 #include <algorithm>
 #include <cstdlib>
 
+#include "common_device.h"
+#include "lds_state.h"
 #include "mars_internal.h"
 
 namespace mars {
+
+// A schedule with no temperature level leaves every run at its initial state
+// (Algorithm 1 with an empty temperature loop): spins = sign of m0 as stored,
+// no sweeps.  Separate from the solver kernels so that their launches are
+// all whole anneals.
+template <typename S>
+__global__ void k_graph_start_only(int N, int R, uint64_t seed, const void *m0, void *m_final, int8_t *spins,
+                                   int64_t *runstat)
+{
+    typedef typename LStore<S>::C C;
+    const int run = blockIdx.y;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const C x = m0 ? (reinterpret_cast<const C *>(m0))[(size_t)i * R + run] : (C)draw_m0(seed, run, i);
+        const C xs = LStore<S>::ld(LStore<S>::st(x));
+        spins[(size_t)run * N + i] = (xs >= (C)0) ? 1 : -1;
+        if (m_final)
+            reinterpret_cast<C *>(m_final)[(size_t)i * R + run] = xs;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 4)
+        runstat[(size_t)run * 4 + threadIdx.x] = 0;
+}
 
 static int env_int(const char *name, int dflt)
 {
@@ -77,6 +100,20 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     a.runstat = g.runstat;
 
     hipError_t e;
+    const RunSchedule rs = make_run_schedule(sc);
+    if (rs.kind == MARS_GEOMETRIC && (rs.first >= rs.steps || rs.count == 0)) {
+        dim3 grid((N + 255) / 256, g.R);
+        if (esz == 8)
+            k_graph_start_only<double><<<grid, 256, 0, s>>>(N, g.R, g.seed, g.m0, g.m_final, g.spins, g.runstat);
+        else if (esz == 4)
+            k_graph_start_only<float><<<grid, 256, 0, s>>>(N, g.R, g.seed, g.m0, g.m_final, g.spins, g.runstat);
+        else
+            k_graph_start_only<_Float16><<<grid, 256, 0, s>>>(N, g.R, g.seed, g.m0, g.m_final, g.spins, g.runstat);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return hip_error(e, "graph start-only launch");
+        return MARS_OK;
+    }
     if (lat) {
         e = launch_lattice_solve(a, (int)esz, rpw, jac, trackd, s);
         if (e != hipSuccess)

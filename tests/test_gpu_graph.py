@@ -100,6 +100,33 @@ def test_jacobi_parity(case, R, precision, levels, tol):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("case", ["er_field", "ea3d_8", "lat_field"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("empty", ["steps", "count"])
+def test_zero_levels(case, precision, empty):
+    """A schedule with no level (steps = 0, or level_count = 0) leaves every
+    run at its draw: m equals the stored m0, spins its signs, energies exact,
+    no sweeps (Algorithm 1 with an empty temperature loop)."""
+    M = _mars()
+    inst = CASES[case]()
+    R = 300
+    kw = dict(steps=0) if empty == "steps" else dict(level_count=0)
+    sch = _rel_sched(inst, precision=precision, **kw)
+    announce("graph zero levels", case, precision, empty)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 5, want_m=True, want_spins=True)
+    ref = O.solve(inst, R, sch.replace(precision="fp64"), 5, run_count=R)
+    m0 = O.initial_m(5, R, inst.N)
+    if precision == "fp16":
+        m0 = m0.astype(np.float16).astype(np.float64)
+    assert np.array_equal(out["m"].cpu().numpy().astype(np.float64), m0)
+    S = out["spins"].cpu().numpy()
+    assert np.array_equal(S, np.where(m0 >= 0, 1, -1).T.astype(np.int8))
+    assert np.array_equal(S, ref["spins"])
+    assert np.array_equal(out["energies"].cpu().numpy(), ref["energy"])
+    assert out["result"]["sweeps_executed"] == 0 and out["result"]["levels_executed"] == 0
+
+
 def _dense_couplings(inst):
     if isinstance(inst, I.LatticeInstance):
         return I.lattice_dense(inst).J.astype(np.float64)
