@@ -90,23 +90,35 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
                 acc[a][b][v] = 0.0f;
 
     ushortx8 ga[PF][LA], gb[PF][LB];
-    // A chunk: run row, 8 spins; spins below p0 from the new buffer.  Both
-    // forms are branch-free, so that the loads of a slab stay in flight
-    // while the previous slab is multiplied: with p0 a multiple of 8 no chunk
-    // straddles p0 and the chunk's buffer is selected; otherwise (BLEND) both
-    // buffers are read and blended element by element.
+    // A chunk: run row, 8 spins; spins below p0 from the new buffer.  The
+    // load is branch-free, so that the loads of a slab stay in flight while
+    // the previous slab is multiplied: each chunk's buffer is selected (a
+    // chunk straddling p0 is read from the old buffer).  When p0 is not a
+    // multiple of 8 (BLEND), the straddling chunk's new-buffer copy is read
+    // once at the start and its spins below p0 are patched in when that
+    // chunk is staged into LDS.
     auto load_a = [&](ushortx8 &dst, int c, int k0) {
         const int row = c / CR, kc = k0 + (c % CR) * 8;
         const size_t off = (size_t)(r0 + row) * ldk + kc;
-        if constexpr (!BLEND) {
-            dst = *reinterpret_cast<const ushortx8 *>((kc < p0 ? Mnew : Mold) + off);
-        } else {
-            const ushortx8 x = *reinterpret_cast<const ushortx8 *>(Mnew + off);
-            const ushortx8 y = *reinterpret_cast<const ushortx8 *>(Mold + off);
+        dst = *reinterpret_cast<const ushortx8 *>((kc + 8 <= p0 ? Mnew : Mold) + off);
+    };
+    const int kst = p0 & ~7;  // start of the chunk that may straddle p0
+    ushortx8 pre[LA];
+    if constexpr (BLEND) {
+#pragma unroll
+        for (int q = 0; q < LA; ++q) {
+            const int row = (tid + q * NT) / CR;
+            pre[q] = *reinterpret_cast<const ushortx8 *>(Mnew + (size_t)(r0 + row) * ldk + kst);
+        }
+    }
+    auto stage_a = [&](ushortx8 v, int q, int k0) -> ushortx8 {
+        if constexpr (BLEND) {
+            const int kc = k0 + ((tid + q * NT) % CR) * 8;
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                dst[e] = (kc + e < p0) ? x[e] : y[e];
+                v[e] = (kc == kst && kst + e < p0) ? pre[q][e] : v[e];
         }
+        return v;
     };
 #define H_LOAD(RA, RB, k0)                                                                          \
     _Pragma("unroll") for (int q = 0; q < LA; ++q)                                                  \
@@ -121,12 +133,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
         if (c_ < CB)                                                                                \
             (RB)[q] = *reinterpret_cast<const ushortx8 *>(J + (size_t)(i0 + c_ / CR) * ldj + (k0) + (c_ % CR) * 8); \
     }
-#define H_STORE(RA, RB, buf)                                                                        \
+#define H_STORE(RA, RB, buf, k0)                                                                    \
     _Pragma("unroll") for (int q = 0; q < LA; ++q)                                                  \
     {                                                                                               \
         const int c_ = tid + q * NT;                                                                \
         if (c_ < CA)                                                                                \
-            *reinterpret_cast<ushortx8 *>(&As[(buf)][c_ / CR][(c_ % CR) * 8]) = (RA)[q];            \
+            *reinterpret_cast<ushortx8 *>(&As[(buf)][c_ / CR][(c_ % CR) * 8]) = stage_a((RA)[q], q, (k0)); \
     }                                                                                               \
     _Pragma("unroll") for (int q = 0; q < LB; ++q)                                                  \
     {                                                                                               \
@@ -148,7 +160,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
         const int kl = s < nk ? s : nk - 1;
         H_LOAD(ga[s], gb[s], kl * BK);
     }
-    H_STORE(ga[0], gb[0], 0);
+    H_STORE(ga[0], gb[0], 0, 0);
     __syncthreads();
     for (int kb = 0; kb < nk; kb += PF) {
 #pragma unroll
@@ -174,7 +186,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
                             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
                 }
                 if (kt + 1 < nk) {
-                    H_STORE(ga[(s + 1) % PF], gb[(s + 1) % PF], cur ^ 1);
+                    H_STORE(ga[(s + 1) % PF], gb[(s + 1) % PF], cur ^ 1, (kt + 1) * BK);
                 }
                 __syncthreads();
             }

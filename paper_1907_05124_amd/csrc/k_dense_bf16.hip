@@ -1,6 +1,7 @@
 // BF16 form of the dense path: conversion of J, state initialisation in the
 // run-major bf16 layout, the phase launcher, and rounding into the padded
 // spin operand shared with the fp32 form (exact energies are unchanged).
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -95,12 +96,31 @@ void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsi
                        dmax);
 }
 
-// Autotuner: the first solve of a (runs, phase width, N) shape times every
-// variant on its first phase (the phase is idempotent: it reads the previous
-// state and writes its own rows), with events on the solve's stream, and
-// keeps the fastest for the process.  MARS_BF16_TILE=<index> forces a variant.
+// Autotuner.  A shape class is (device, runs / 128, phase width / 128, N /
+// 1024, capped at 8), rounded up.  The first solve of a class enqueues, on
+// its own stream and before its first sweep, two launches of every variant
+// on the first phase between timing events (the phase is idempotent: it
+// reads the previous state and writes its own rows) and uses the default
+// variant; a later solve of the class reads the events once they have
+// completed and keeps the fastest variant for the process.  Nothing blocks
+// the host.  MARS_BF16_TILE=<index> forces a variant.
+struct TuneEntry {
+    bool decided = false;
+    int chosen = 0;
+    hipEvent_t ev[kNumBf16Variants][2] = {};
+};
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int>, int> g_tune_cache;
+static std::map<std::tuple<int, int, int, int>, TuneEntry> g_tune_cache;
+
+static void destroy_events(TuneEntry &t)
+{
+    for (auto &p : t.ev)
+        for (auto &e : p)
+            if (e) {
+                (void)hipEventDestroy(e);
+                e = nullptr;
+            }
+}
 
 int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R, int p0,
                        int p1, const float *invT, float gamma, hipStream_t s)
@@ -110,42 +130,51 @@ int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned s
         if (v >= 0 && v < kNumBf16Variants)
             return v;
     }
-    const auto key = std::make_tuple(R, p1 - p0, I.N);
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end())
-            return it->second;
-    }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int best = 0;
-    float best_ms = 0.0f;
-    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
-    for (int v = 0; ok && v < kNumBf16Variants; ++v) {
-        launch_dense_phase_bf16(I, Mold, Mnew, ldk, R, p0, p1, invT, gamma, nullptr, v, s);  // warm
-        ok = hipEventRecord(e0, s) == hipSuccess;
-        for (int r = 0; ok && r < 3; ++r)
-            launch_dense_phase_bf16(I, Mold, Mnew, ldk, R, p0, p1, invT, gamma, nullptr, v, s);
-        ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, s) == hipSuccess &&
-             hipEventSynchronize(e1) == hipSuccess;
-        float ms = 0.0f;
-        ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-        if (ok && (v == 0 || ms < best_ms)) {
-            best = v;
-            best_ms = ms;
-        }
-    }
-    if (e0)
-        (void)hipEventDestroy(e0);
-    if (e1)
-        (void)hipEventDestroy(e1);
-    if (!ok) {
-        (void)hipGetLastError();  // clear a failed timing; the default variant is used
-        return 0;
-    }
+    const auto key = std::make_tuple(I.device, (R + 127) / 128, (p1 - p0 + 127) / 128, std::min((I.N + 1023) / 1024, 8));
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_cache[key] = best;
-    return best;
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+        TuneEntry &t = it->second;
+        if (t.decided)
+            return t.chosen;
+        // pending: decide once every timing event has completed
+        for (auto &p : t.ev)
+            if (hipEventQuery(p[1]) != hipSuccess)
+                return 0;
+        float best_ms = 0.0f;
+        for (int v = 0; v < kNumBf16Variants; ++v) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, t.ev[v][0], t.ev[v][1]) != hipSuccess) {
+                (void)hipGetLastError();
+                t.chosen = 0;
+                break;
+            }
+            if (v == 0 || ms < best_ms) {
+                best_ms = ms;
+                t.chosen = v;
+            }
+        }
+        destroy_events(t);
+        t.decided = true;
+        return t.chosen;
+    }
+    TuneEntry &t = g_tune_cache[key];
+    bool ok = true;
+    for (int v = 0; ok && v < kNumBf16Variants; ++v) {
+        ok = hipEventCreate(&t.ev[v][0]) == hipSuccess && hipEventCreate(&t.ev[v][1]) == hipSuccess &&
+             hipEventRecord(t.ev[v][0], s) == hipSuccess;
+        for (int r = 0; ok && r < 2; ++r)
+            launch_dense_phase_bf16(I, Mold, Mnew, ldk, R, p0, p1, invT, gamma, nullptr, v, s);
+        ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(t.ev[v][1], s) == hipSuccess;
+    }
+    if (!ok) {
+        // timing unavailable: keep the default variant for this class
+        (void)hipGetLastError();
+        destroy_events(t);
+        t.decided = true;
+        t.chosen = 0;
+    }
+    return 0;
 }
 
 // s = +1 if m >= 0 else -1 into the padded operand [ldr x Ke]; optional
