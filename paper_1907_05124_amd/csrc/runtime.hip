@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "common_device.h"
@@ -104,21 +105,26 @@ static void destroy_instance(Instance *I)
 // fixed point for exact energies
 // ---------------------------------------------------------------------------
 
-// Exponent of the lowest set bit of a nonzero finite float.
+// A nonzero finite float is an integer mantissa m times 2^q (normal: m has
+// its implicit bit, q = biased exponent - 150; subnormal: q = -149).
+// Exponent of its lowest set bit: q + ctz(m).
 static int low_bit_exponent(float v)
 {
-    int e;
-    float f = std::frexp(std::fabs(v), &e);  // v = f * 2^e, f in [0.5, 1)
-    uint32_t m = (uint32_t)std::ldexp(f, 24);  // 24-bit integer mantissa (exact)
-    int tz = __builtin_ctz(m);
-    return e - 24 + tz;
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    const uint32_t be = (u >> 23) & 0xffu, m = (u & 0x7fffffu) | (be ? 0x800000u : 0u);
+    const int q = be ? (int)be - 150 : -149;
+    return q + __builtin_ctz(m);
 }
 
+// The e with 2^(e-1) <= |v| < 2^e: q + (number of bits of m).
 static int high_bit_exponent(float v)
 {
-    int e;
-    (void)std::frexp(std::fabs(v), &e);
-    return e;  // |v| < 2^e
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    const uint32_t be = (u >> 23) & 0xffu, m = (u & 0x7fffffu) | (be ? 0x800000u : 0u);
+    const int q = be ? (int)be - 150 : -149;
+    return q + (32 - __builtin_clz(m));
 }
 
 // Bit budget: every term is a multiple of 2^emin below 2^emax.  Row sums of
@@ -217,32 +223,108 @@ static mars_status upload_h(Instance *I, const float *h, int padN)
     return MARS_OK;
 }
 
+// Validation scan of dense couplings, rows split over host threads.  Pass 1
+// checks every value is finite.  Pass 2 walks 64 x 64 tiles of the upper
+// triangle (the transposed tile stays in cache): zero diagonal, bitwise
+// symmetry, the fixed-point exponent range, and row sums kept per row and
+// added in row order afterwards (independent of the thread count).  A
+// fault is reported for the lowest row that has one, diagonal before
+// symmetry, as a row-by-row scan would.
+struct DenseScan {
+    FixInfo fx;
+    bool nonfinite = false;
+    long long fault_row = -1;  // lowest row with a diagonal (2) or symmetry (3) fault
+    int fault = 0;
+    void note(long long row, int kind)
+    {
+        if (fault_row < 0 || row < fault_row || (row == fault_row && kind < fault)) {
+            fault_row = row;
+            fault = kind;
+        }
+    }
+};
+
+static void scan_dense_tile_row(const float *J, long long N, long long bi, std::vector<double> &rowsum, DenseScan &out)
+{
+    constexpr long long TB = 64;
+    const long long i0 = bi * TB, i1 = std::min(N, i0 + TB);
+    for (long long i = i0; i < i1; ++i)
+        if (J[i * N + i] != 0.0f)
+            out.note(i, 2);
+    for (long long j0 = i0; j0 < N; j0 += TB) {
+        const long long j1 = std::min(N, j0 + TB);
+        for (long long i = i0; i < i1; ++i) {
+            double rs = 0.0;
+            for (long long j = std::max(j0, i + 1); j < j1; ++j) {
+                const float a = J[i * N + j], b = J[j * N + i];
+                uint32_t ua, ub;
+                std::memcpy(&ua, &a, 4);
+                std::memcpy(&ub, &b, 4);
+                if (ua != ub)
+                    out.note(i, 3);
+                out.fx.add(a);
+                rs += (double)a;
+            }
+            rowsum[(size_t)i] += rs;
+        }
+    }
+}
+
 static mars_status create_dense(const float *J, const float *h, int N, Instance *I)
 {
     I->kind = KIND_DENSE;
     I->N = N;
     FixInfo fx;
     double wsum = 0.0;
-    for (long long i = 0; i < N; ++i) {
-        for (long long j = 0; j < N; ++j) {
-            float v = J[i * N + j];
-            if (!std::isfinite(v))
+    {
+        const long long nb = ((long long)N + 63) / 64;
+        int nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+        nt = (int)std::min<long long>(nt, std::max(1ll, nb / 4));
+        std::vector<double> rowsum((size_t)N, 0.0);
+        std::vector<DenseScan> part((size_t)nt);
+        auto run = [&](auto &&fn) {
+            std::vector<std::thread> pool;
+            for (int t = 1; t < nt; ++t)
+                pool.emplace_back(fn, t);
+            fn(0);
+            for (auto &th : pool)
+                th.join();
+        };
+        const long long NN = (long long)N * N;
+        run([&](int t) {
+            const long long a = NN * t / nt, b = NN * (t + 1) / nt;
+            for (long long k = a; k < b; ++k)
+                if (!std::isfinite(J[k])) {
+                    part[(size_t)t].nonfinite = true;
+                    return;
+                }
+        });
+        for (const DenseScan &d : part)
+            if (d.nonfinite)
                 return set_error(MARS_E_NONFINITE, "J contains a non-finite value");
+        // interleaved tile rows balance the triangle's uneven row lengths; a
+        // thread stops after the first tile row where it found a fault
+        run([&](int t) {
+            for (long long bi = t; bi < nb && part[(size_t)t].fault == 0; bi += nt)
+                scan_dense_tile_row(J, N, bi, rowsum, part[(size_t)t]);
+        });
+        const DenseScan *first = nullptr;
+        for (const DenseScan &d : part) {
+            if (d.fault && (!first || d.fault_row < first->fault_row ||
+                            (d.fault_row == first->fault_row && d.fault < first->fault)))
+                first = &d;
+            if (d.fx.any) {
+                fx.emin = fx.any ? std::min(fx.emin, d.fx.emin) : d.fx.emin;
+                fx.emax = fx.any ? std::max(fx.emax, d.fx.emax) : d.fx.emax;
+                fx.any = true;
+            }
         }
-    }
-    for (long long i = 0; i < N; ++i) {
-        if (J[i * N + i] != 0.0f)
+        if (first && first->fault == 2)
             return set_error(MARS_E_DIAGONAL, "J has a nonzero diagonal entry (the energy sums j != i)");
-        for (long long j = i + 1; j < N; ++j) {
-            float a = J[i * N + j], b = J[j * N + i];
-            uint32_t ua, ub;
-            std::memcpy(&ua, &a, 4);
-            std::memcpy(&ub, &b, 4);
-            if (ua != ub)
-                return set_error(MARS_E_ASYMMETRIC, "J is not symmetric (bitwise)");
-            fx.add(a);
-            wsum -= 2.0 * (double)a;
-        }
+        if (first)
+            return set_error(MARS_E_ASYMMETRIC, "J is not symmetric (bitwise)");
+        for (int i = 0; i < N; ++i)
+            wsum -= 2.0 * rowsum[(size_t)i];
     }
     mars_status st = check_h(h, N, fx);
     if (st != MARS_OK)

@@ -232,3 +232,60 @@ def test_bench_configuration_sampled_runs():
     # the summary refers to the full set of runs
     res = out["result"]
     assert res["best_energy"] == E.min() and res["spin_updates"] == R * 300 * inst.N
+
+
+@pytest.mark.parametrize("N", [5, 300, 1100])
+def test_dense_create_validation(N):
+    """Instance validation (parallel, tiled scan): each malformed input gets its
+    status; with several faults the first one in row-by-row order decides: a
+    non-finite value anywhere first, then the lowest row with a diagonal
+    entry or an asymmetric pair (j > i), the diagonal first within a row."""
+    M = _mars()
+    base = I.sk_instance(N, 8).J
+
+    def status(J):
+        try:
+            M.Instance.dense(J).close()
+        except M.MarsError as e:
+            return e.status
+        return 0
+
+    assert status(base) == 0
+    A = base.copy()
+    A[N - 1, 0] = np.nextafter(A[N - 1, 0], np.float32(2.0))  # pair (0, N-1) differs: found in row 0
+    assert status(A) == 2
+    AD = A.copy()
+    AD[N // 2, N // 2] = 0.5  # a later row's diagonal does not win over row 0
+    assert status(AD) == 2
+    D = base.copy()
+    D[N // 2, N // 2] = 0.5
+    assert status(D) == 3
+    DA = D.copy()
+    DA[N // 2, N - 1] += np.float32(1.0)  # same row: the diagonal wins
+    assert status(DA) == 3
+    F = DA.copy()
+    F[N - 1, N - 2] = np.nan  # a non-finite value anywhere wins
+    assert status(F) == 4
+
+
+@pytest.mark.parametrize("kind", ["subnormal", "wide"])
+def test_dense_exponent_range_pins(kind):
+    """The fixed point covers every coupling exactly (subnormal couplings, or
+    normal ones spanning ~50 bits): energies equal the exactly rounded sums."""
+    M = _mars()
+    torch = require_gpu()
+    N = 40
+    rng = np.random.default_rng(9)
+    J = rng.standard_normal((N, N)).astype(np.float32)
+    if kind == "subnormal":
+        J = (J * np.float32(1e-40)).astype(np.float32)
+        assert np.all(np.abs(J[J != 0]) < np.finfo(np.float32).tiny)
+    else:
+        J[0, 1] = np.float32(2.0**20 + 1.0)
+    J = np.triu(J, 1)
+    J = (J + J.T).astype(np.float32)
+    inst = I.DenseInstance(J=J, h=None)
+    S = I.random_spins(N, 12, 4)
+    with M.Instance.from_inputs(inst) as g:
+        E = g.energy(torch.from_numpy(S).cuda()).cpu().numpy()
+    assert np.array_equal(E, O.energy(inst, S))
