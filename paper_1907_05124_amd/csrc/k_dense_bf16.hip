@@ -13,8 +13,8 @@
 
 namespace mars {
 
-// Tile variants of the phase kernel (register prefetch ring of two slabs,
-// measured fastest on the SK N=2000 x 4096-run shape).  Every variant reduces each output
+// Tile variants of the phase kernel (register prefetch ring of two slabs;
+// 64- or 128-deep slabs, both visiting K in the same order).  Every variant reduces each output
 // element over K in the same order (64-deep slabs, one wave per 32 x 32
 // block), so all of them produce bitwise identical results; they differ in
 // how many workgroups a phase yields.  128 x 128 x 16 waves is the fastest on
@@ -25,19 +25,20 @@ typedef void (*Bf16PhaseFn)(const unsigned short *, int, const unsigned short *,
 // fn_aligned: the phase starts at a multiple of 8 spins (no 8-spin chunk
 // straddles it); fn_blend: any start.
 struct Bf16Variant {
-    int bm, bn, threads;
+    int bm, bn, bk, threads;
     Bf16PhaseFn fn_aligned, fn_blend;
 };
-#define BF16_VARIANT(BM, BN, WM, WN, PF)                                                          \
+#define BF16_VARIANT(BM, BN, WM, WN, PF, BK)                                                      \
     {                                                                                           \
-        BM, BN, 64 * WM * WN, k_dense_phase_bf16<BM, BN, WM, WN, PF, HBK, false>,              \
-            k_dense_phase_bf16<BM, BN, WM, WN, PF, HBK, true>                                   \
+        BM, BN, BK, 64 * WM * WN, k_dense_phase_bf16<BM, BN, WM, WN, PF, BK, false>,           \
+            k_dense_phase_bf16<BM, BN, WM, WN, PF, BK, true>                                    \
     }
 static const Bf16Variant kBf16Variants[] = {
-    BF16_VARIANT(128, 128, 4, 4, 2),
-    BF16_VARIANT(64, 128, 2, 4, 2),
-    BF16_VARIANT(128, 64, 4, 2, 2),
-    BF16_VARIANT(64, 64, 2, 2, 2),
+    BF16_VARIANT(128, 128, 4, 4, 2, 64),
+    BF16_VARIANT(64, 128, 2, 4, 2, 64),
+    BF16_VARIANT(128, 64, 4, 2, 2, 64),
+    BF16_VARIANT(64, 64, 2, 2, 2, 64),
+    BF16_VARIANT(128, 128, 4, 4, 2, 128),
 };
 #undef BF16_VARIANT
 constexpr int kNumBf16Variants = sizeof(kBf16Variants) / sizeof(kBf16Variants[0]);
@@ -90,7 +91,7 @@ void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsi
     const Bf16Variant &v = kBf16Variants[(variant >= 0 && variant < kNumBf16Variants) ? variant : 0];
     const int nrt = (R + v.bm - 1) / v.bm;
     const int nct = (p1 - p0 + v.bn - 1) / v.bn;
-    const int kpad = (I.N + HBK - 1) / HBK * HBK;
+    const int kpad = (I.N + v.bk - 1) / v.bk * v.bk;  // within the zero-padded Np columns
     hipLaunchKernelGGL((p0 % 8 == 0) ? v.fn_aligned : v.fn_blend, dim3(nrt * nct), dim3(v.threads), 0, s, I.Jbf,
                        I.Np, Mold, Mnew, ldk, R, p0, p1, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma,
                        dmax);

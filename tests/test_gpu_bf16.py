@@ -69,7 +69,7 @@ def test_bf16_one_level(N, R, phases, field):
     assert np.all(err <= tol), float(np.max(err / tol))
 
 
-@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4"])
 def test_bf16_tile_variants_bitwise(tile, monkeypatch):
     """The autotuner may pick any tile variant: every variant reduces each
     element over K in the same order, so a 20-level anneal with a forced
@@ -89,7 +89,7 @@ def test_bf16_tile_variants_bitwise(tile, monkeypatch):
     assert np.array_equal(a["energies"].cpu().numpy(), b["energies"].cpu().numpy())
 
 
-@pytest.mark.parametrize("tile", ["1", "3"])
+@pytest.mark.parametrize("tile", ["1", "3", "4"])
 def test_bf16_one_level_small_tiles(tile, monkeypatch):
     """One level on a forced small-tile variant, same bar as the default tile."""
     monkeypatch.setenv("MARS_BF16_TILE", tile)
