@@ -202,6 +202,8 @@ def main():
         forms = [args.precision]
     elif dense:
         forms = ["fp32", "bf16"]  # the exact-arithmetic form and the bf16 matrix-core form
+    elif isinstance(w.instance, I.CsrInstance) and w.schedule.precision == "fp32":
+        forms = ["fp32", "fp16"]  # fp32 state, and fp16 state storage with fp32 fields (twice the runs per CU)
     else:
         forms = [w.schedule.precision]
 
