@@ -195,6 +195,48 @@ mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_sched
  * the call returns after enqueueing.  Errors: MARS_E_ARG, MARS_E_DEVICE. */
 mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, double *energies, void *stream);
 
+/* Batched BF16 solver for a served stream of dense instances (the BF16 form
+ * of the dense field product, Algorithm 1's update, eq. (2) energies): the
+ * members of a batch advance together on one stream and every update phase
+ * of every member is ONE launch over all their tiles, so instances of uneven
+ * N share the GPU instead of each underfilling it.  Members join and leave
+ * between sweeps (continuous batching); each member is at its own level.
+ * Results equal mars_solve_async's for the same arguments bit for bit.
+ *
+ * mars_batch_create: stream is a hipStream_t (NULL: the default stream) on
+ *   the current device; the batch owns no device memory.  Errors: MARS_E_ARG
+ *   (out NULL), MARS_E_OOM.
+ * mars_batch_add: enqueues the member's set-up (its workspace, starting
+ *   temperatures, level table, initial state) on the batch stream; it joins
+ *   at the next step.  inst: a dense instance on the batch's device, owned by
+ *   the batch (no other call may use it) until the member finishes.  sched:
+ *   precision MARS_BF16, max_sweeps 1 (one sweep per level).  tag: returned
+ *   by mars_batch_step when the member finishes.  best_spins: DEVICE int8 [N]
+ *   or NULL; res_pinned: HOST mars_result in pinned memory, or NULL; both
+ *   are written by the stream when the member finishes.  Errors: MARS_E_ARG,
+ *   MARS_E_UNSUPPORTED (not dense, not MARS_BF16, max_sweeps != 1, another
+ *   device, or the batch already holds 16 members), MARS_E_OOM, MARS_E_DEVICE.
+ * mars_batch_step: enqueues up to `sweeps` sweeps of every member; a member
+ *   that reaches its last level is rounded and scored, its outputs are
+ *   copied, and it leaves.  finished_tags: HOST int64 [cap] receiving the tags
+ *   of the members that left during this call (*n_finished of them, never
+ *   more than cap: a finished member beyond that stays, without sweeping,
+ *   and leaves at a later call; sweeps = 0 only retires); *n_active: members
+ *   still in the batch.  Outputs of a finished member are valid once
+ *   the stream has passed the work enqueued by the call.  Errors: MARS_E_ARG,
+ *   MARS_E_DEVICE.
+ * mars_batch_destroy: waits for the batch stream and releases the batch and
+ *   every member still in it (their outputs are not written).  NULL is a
+ *   no-op.  An instance is destroyed only after its member has finished or
+ *   its batch has been destroyed. */
+typedef struct mars_batch mars_batch;
+mars_status mars_batch_create(void *stream, mars_batch **out);
+mars_status mars_batch_add(mars_batch *batch, mars_instance *inst, int32_t runs, const mars_schedule *sched,
+                           uint64_t seed, int64_t tag, int8_t *best_spins, mars_result *res_pinned);
+mars_status mars_batch_step(mars_batch *batch, int32_t sweeps, int64_t *finished_tags, int32_t cap,
+                            int32_t *n_finished, int32_t *n_active);
+void mars_batch_destroy(mars_batch *batch);
+
 /* Static description of a status code, and the last error message of the
  * calling thread (empty if none).  Both strings stay owned by the library. */
 const char *mars_status_str(mars_status s);

@@ -47,11 +47,21 @@ __device__ inline float bf16_form_tanh(float x)
     return copysignf(t, x);
 }
 
-template <int BM, int BN, int WM, int WN, int PF, int BK = HBK, bool BLEND = true>
-__global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
+// LDS of one workgroup: double-buffered A and B slabs, rows padded by 8
+template <int BM, int BN, int BK>
+constexpr size_t bf16_phase_lds_bytes()
+{
+    return (size_t)2 * (BM + BN) * (BK + 8) * sizeof(unsigned short);
+}
+
+// One workgroup tile of a phase: tile t (0 <= t < nrt * nct) of the phase's
+// grid; lds: bf16_phase_lds_bytes<BM, BN, BK>() bytes, 16-byte aligned.
+template <int BM, int BN, int WM, int WN, int PF, int BK, bool BLEND>
+__device__ __forceinline__ void bf16_phase_tile(
     const unsigned short *__restrict__ J, int ldj, const unsigned short *__restrict__ Mold,
     unsigned short *__restrict__ Mnew, int ldk, int R, int p0, int p1, int nrt, int nct, int kpad,
-    const float *__restrict__ invT, const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax)
+    const float *__restrict__ invT, const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax,
+    unsigned char *lds, int tile)
 {
     constexpr int NT = 64 * WM * WN;
     constexpr int TM = BM / WM, TN = BN / WN;
@@ -63,8 +73,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
     static_assert(MB >= 1 && NB >= 1, "tile shape");
     static_assert(PF >= 1 && PF <= 4, "prefetch ring");
 
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][BM][LDR];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN][LDR];
+    typedef unsigned short ATile[BM][LDR];
+    typedef unsigned short BTile[BN][LDR];
+    ATile *As = reinterpret_cast<ATile *>(lds);
+    BTile *Bs = reinterpret_cast<BTile *>(lds + (size_t)2 * BM * LDR * sizeof(unsigned short));
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -73,7 +85,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
 
     // tile order: the workgroups of one XCD share a band of runs (rows of M^T)
     const int total = nrt * nct;
-    int t = blockIdx.x;
+    int t = tile;
     if ((total & 7) == 0)
         t = (t & 7) * (total >> 3) + (t >> 3);
     const int rt = t / nct, ct = t % nct;
@@ -250,6 +262,59 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
             }
         }
     }
+}
+
+template <int BM, int BN, int WM, int WN, int PF, int BK = HBK, bool BLEND = true>
+__global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16(
+    const unsigned short *__restrict__ J, int ldj, const unsigned short *__restrict__ Mold,
+    unsigned short *__restrict__ Mnew, int ldk, int R, int p0, int p1, int nrt, int nct, int kpad,
+    const float *__restrict__ invT, const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char lds[bf16_phase_lds_bytes<BM, BN, BK>()];
+    bf16_phase_tile<BM, BN, WM, WN, PF, BK, BLEND>(J, ldj, Mold, Mnew, ldk, R, p0, p1, nrt, nct, kpad, invT, hhalf,
+                                                   gamma, dmax, lds, blockIdx.x);
+}
+
+// One phase of several dense instances in one launch (the batched solver):
+// instance i owns workgroups [tile0_i, tile0_i + nrt_i * nct_i); tile0 is a
+// multiple of 8, so that a workgroup's position inside its instance's grid
+// keeps the XCD it would have alone (the gaps are workgroups that exit).
+struct Bf16PhaseDesc {
+    const unsigned short *J;
+    const unsigned short *Mold;
+    unsigned short *Mnew;
+    const float *invT;
+    const float *hhalf;
+    int ldj, ldk, R, p0, p1, nrt, nct, kpad;
+    float gamma;
+    int tile0;
+    int blend;  // p0 is not a multiple of 8
+};
+
+constexpr int kMaxBatch = 16;  // instances per grouped launch (descriptors travel as kernel arguments)
+struct Bf16GroupArgs {
+    int n;
+    Bf16PhaseDesc d[kMaxBatch];
+};
+
+template <int BM, int BN, int WM, int WN, int PF, int BK>
+__global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_bf16_group(Bf16GroupArgs args)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char lds[bf16_phase_lds_bytes<BM, BN, BK>()];
+    const int g = blockIdx.x;
+    int i = 0;
+    while (i + 1 < args.n && args.d[i + 1].tile0 <= g)
+        ++i;
+    const Bf16PhaseDesc d = args.d[i];
+    const int t = g - d.tile0;
+    if (t >= d.nrt * d.nct)
+        return;
+    if (d.blend)
+        bf16_phase_tile<BM, BN, WM, WN, PF, BK, true>(d.J, d.ldj, d.Mold, d.Mnew, d.ldk, d.R, d.p0, d.p1, d.nrt, d.nct,
+                                                      d.kpad, d.invT, d.hhalf, d.gamma, nullptr, lds, t);
+    else
+        bf16_phase_tile<BM, BN, WM, WN, PF, BK, false>(d.J, d.ldj, d.Mold, d.Mnew, d.ldk, d.R, d.p0, d.p1, d.nrt, d.nct,
+                                                       d.kpad, d.invT, d.hhalf, d.gamma, nullptr, lds, t);
 }
 
 }  // namespace mars

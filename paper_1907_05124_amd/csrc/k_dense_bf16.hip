@@ -178,6 +178,41 @@ int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned s
     return 0;
 }
 
+static_assert(kMaxBatch == kMaxBatchMembers, "grouped launch capacity");
+
+// One phase of several instances in one launch (128 x 128 tiles, 16 waves).
+hipError_t launch_dense_phase_bf16_group(const Bf16GroupMember *m, int n, hipStream_t s)
+{
+    if (n < 1 || n > kMaxBatch)
+        return hipErrorInvalidValue;
+    Bf16GroupArgs a;
+    a.n = n;
+    int tile0 = 0;
+    for (int i = 0; i < n; ++i) {
+        const Instance &I = *m[i].I;
+        Bf16PhaseDesc &d = a.d[i];
+        d.J = I.Jbf;
+        d.Mold = m[i].Mold;
+        d.Mnew = m[i].Mnew;
+        d.invT = m[i].invT;
+        d.hhalf = I.has_h ? I.hhalf : nullptr;
+        d.ldj = I.Np;
+        d.ldk = I.Np;
+        d.R = m[i].R;
+        d.p0 = m[i].p0;
+        d.p1 = m[i].p1;
+        d.nrt = (m[i].R + 127) / 128;
+        d.nct = (m[i].p1 - m[i].p0 + 127) / 128;
+        d.kpad = (I.N + HBK - 1) / HBK * HBK;
+        d.gamma = m[i].gamma;
+        d.tile0 = tile0;
+        d.blend = (m[i].p0 % 8) != 0;
+        tile0 += (d.nrt * d.nct + 7) / 8 * 8;  // next instance starts on a multiple of 8
+    }
+    hipLaunchKernelGGL((k_dense_phase_bf16_group<128, 128, 4, 4, 2, HBK>), dim3(tile0), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
 // s = +1 if m >= 0 else -1 into the padded operand [ldr x Ke]; optional
 // caller spins [R x N] and fp32 magnetisations [N x R]
 __global__ void k_bf16_round(const unsigned short *MT, int ldk, int N, int R, int Ke, int ldr, int8_t *spad,

@@ -92,6 +92,7 @@ struct Instance {
     // stream first waits for the previous one (recorded in done_event)
     hipEvent_t done_event = nullptr;
     bool done_recorded = false;
+    bool in_batch = false;  // owned by a batch until its member finishes
     Workspace ws;
     std::mutex mu;
 };
@@ -148,8 +149,35 @@ void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsi
                              hipStream_t s);
 int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R, int p0,
                        int p1, const float *invT, float gamma, hipStream_t s);
+// one member of a grouped phase launch (the batched solver)
+struct Bf16GroupMember {
+    const Instance *I;
+    const unsigned short *Mold;
+    unsigned short *Mnew;
+    const float *invT;  // this member's level row of 1/T
+    int R, p0, p1;
+    float gamma;
+};
+constexpr int kMaxBatchMembers = 16;
+hipError_t launch_dense_phase_bf16_group(const Bf16GroupMember *m, int n, hipStream_t s);
 void launch_bf16_round(const unsigned short *MT, int ldk, int N, int R, int Ke, int8_t *spad, int8_t *spins,
                        float *m_final, hipStream_t s);
+
+// dense solve stages (runtime.hip), shared by single solves and the batch
+struct DenseRun {
+    int R = 0, ldm = 0, ldr = 0, ldt = 0, kmax = 0, B = 0;
+    std::vector<int> pb;  // phase bounds [B + 1]
+    bool bf16 = false;
+    float gamma = 1.0f;
+    double *T0 = nullptr;
+    float *table = nullptr;  // [kmax x ldt] 1/T per level and run, -1 past a run's levels
+    int32_t *nlev = nullptr;
+    void *Ma = nullptr, *Mb = nullptr;  // state ping-pong buffers (Ma holds the initial state)
+};
+mars_status dense_setup(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const float *m0,
+                        const double *T0in, DenseRun &d, hipStream_t s);
+mars_status dense_finish(Instance *I, const DenseRun &d, const void *cur, float *m_final, int8_t *spins, double *E,
+                         int8_t *best_spins, mars_result *res_dev, int32_t *best_dev, hipStream_t s);
 
 // graph (lattice and csr): the whole anneal of a block of runs in LDS
 struct GraphSolve {

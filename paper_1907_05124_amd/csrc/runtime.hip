@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -669,31 +670,34 @@ static mars_status max_levels(const mars_schedule &sc, double Tmax, int *out)
     return MARS_OK;
 }
 
-static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const float *m0,
-                               const double *T0in, float *m_final, int8_t *spins, double *E, int8_t *best_spins,
-                               mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+// Dense solve, first stage: buffers, starting temperatures, the level table
+// and the initial state (Algorithm 1's random start), enqueued on s.
+mars_status dense_setup(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const float *m0,
+                        const double *T0in, DenseRun &d, hipStream_t s)
 {
     if (sc.precision != MARS_FP32 && sc.precision != MARS_BF16)
         return set_error(MARS_E_UNSUPPORTED, "dense instances support MARS_FP32 and MARS_BF16");
-    const bool bf16 = sc.precision == MARS_BF16;
+    d.bf16 = sc.precision == MARS_BF16;
     Workspace &w = I->ws;
     const int N = I->N;
     mars_status st;
-    if (bf16 && (st = ensure_bf16_couplings(*I, s)) != MARS_OK)
+    if (d.bf16 && (st = ensure_bf16_couplings(*I, s)) != MARS_OK)
         return st;
     // state: fp32 [Np x ldm] spin-major, or bf16 [ldr x Np] run-major
-    const int ldm = ((R + 127) / 128) * 128;
-    const int ldr = bf16_state_rows(R);
-    const size_t mbytes = bf16 ? sizeof(unsigned short) * (size_t)ldr * I->Np : sizeof(float) * (size_t)I->Np * ldm;
+    d.R = R;
+    d.ldm = ((R + 127) / 128) * 128;
+    d.ldr = bf16_state_rows(R);
+    const size_t mbytes =
+        d.bf16 ? sizeof(unsigned short) * (size_t)d.ldr * I->Np : sizeof(float) * (size_t)I->Np * d.ldm;
     if ((st = ensure(w.Ma, mbytes)) || (st = ensure(w.Mb, mbytes)) || (st = ensure(w.T0, sizeof(double) * R)) ||
         (st = ensure(w.nlev, sizeof(int32_t) * R)) || (st = ensure(w.runstat, sizeof(int64_t) * 4 * R)) ||
-        (st = ensure(w.dmax, sizeof(uint32_t) * ldr)) || (st = ensure(w.runstate, sizeof(int32_t) * 4 * ldr)) ||
+        (st = ensure(w.dmax, sizeof(uint32_t) * d.ldr)) || (st = ensure(w.runstate, sizeof(int32_t) * 4 * d.ldr)) ||
         (st = ensure(w.flag, 64)))
         return st;
     launch_fill_u32((uint32_t *)w.Ma.p, 0u, mbytes / 4, s);
     launch_fill_u32((uint32_t *)w.Mb.p, 0u, mbytes / 4, s);
-    double *T0 = (double *)w.T0.p;
-    launch_init_T0(seed, R, sc.T_lo, sc.T_hi, T0in, T0, s);
+    d.T0 = (double *)w.T0.p;
+    launch_init_T0(seed, R, sc.T_lo, sc.T_hi, T0in, d.T0, s);
     double Tmax = sc.T_hi;
     if (T0in && sc.kind == MARS_LINEAR) {
         std::vector<double> h((size_t)R);
@@ -703,27 +707,68 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
         if (!std::isfinite(Tmax))
             return set_error(MARS_E_ARG, "T0 contains a non-finite value");
     }
-    int kmax = 0;
-    if ((st = max_levels(sc, Tmax, &kmax)) != MARS_OK)
+    if ((st = max_levels(sc, Tmax, &d.kmax)) != MARS_OK)
         return st;
-    if ((st = ensure(w.invT, sizeof(float) * (size_t)std::max(kmax, 1) * ldr)) != MARS_OK)
+    if ((st = ensure(w.invT, sizeof(float) * (size_t)std::max(d.kmax, 1) * d.ldr)) != MARS_OK)
         return st;
     // one table row per level; ldr >= ldm, so the same stride serves both forms
-    const int ldt = ldr;
-    float *table = (float *)w.invT.p;
-    int32_t *nlev = (int32_t *)w.nlev.p;
-    launch_level_table(sc, R, T0, kmax, ldt, table, nullptr, nlev, s);
-    if (bf16)
+    d.ldt = d.ldr;
+    d.table = (float *)w.invT.p;
+    d.nlev = (int32_t *)w.nlev.p;
+    launch_level_table(sc, R, d.T0, d.kmax, d.ldt, d.table, nullptr, d.nlev, s);
+    if (d.bf16)
         launch_bf16_init_state(seed, N, R, I->Np, m0, (unsigned short *)w.Ma.p, s);
     else
-        launch_dense_init_state(seed, N, R, ldm, m0, (float *)w.Ma.p, s);
+        launch_dense_init_state(seed, N, R, d.ldm, m0, (float *)w.Ma.p, s);
+    d.B = sc.update == MARS_JACOBI ? 1 : std::min(sc.phases, N);
+    d.pb.assign((size_t)d.B + 1, 0);
+    for (int b = 0; b <= d.B; ++b)
+        d.pb[b] = (int)((long long)b * N / d.B);
+    d.gamma = (float)sc.damping;
+    d.Ma = w.Ma.p;
+    d.Mb = w.Mb.p;
+    return MARS_OK;
+}
 
-    const int B = sc.update == MARS_JACOBI ? 1 : std::min(sc.phases, N);
-    std::vector<int> pb((size_t)B + 1);
-    for (int b = 0; b <= B; ++b)
-        pb[b] = (int)((long long)b * N / B);
-    const float gamma = (float)sc.damping;
-    void *cur = w.Ma.p, *nxt = w.Mb.p;
+// Dense solve, last stage: round the final state (cur), exact energies,
+// best of runs.
+mars_status dense_finish(Instance *I, const DenseRun &d, const void *cur, float *m_final, int8_t *spins, double *E,
+                         int8_t *best_spins, mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+{
+    Workspace &w = I->ws;
+    const int N = I->N, R = d.R;
+    mars_status st;
+    if ((st = ensure(w.spad, dense_spin_operand_bytes(*I, R))) != MARS_OK)
+        return st;
+    int8_t *spad = (int8_t *)w.spad.p;
+    if (d.bf16)
+        launch_bf16_round((const unsigned short *)cur, I->Np, N, R, I->Ke, spad, spins, m_final, s);
+    else
+        launch_dense_round((const float *)cur, d.ldm, N, R, I->Ke, spad, spins, m_final, s);
+    launch_dense_energy_i8(*I, spad, R, E, I->ws.partial.p, s);
+    launch_argmin(E, d.T0, (const int64_t *)w.runstat.p, R, N, I->wsum, res_dev, best_dev, s);
+    if (best_spins)
+        launch_gather_best(spad, I->Ke, best_dev, N, best_spins, s);
+    MARS_HIP(hipGetLastError());
+    return MARS_OK;
+}
+
+static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const float *m0,
+                               const double *T0in, float *m_final, int8_t *spins, double *E, int8_t *best_spins,
+                               mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+{
+    DenseRun d;
+    mars_status st = dense_setup(I, R, sc, seed, m0, T0in, d, s);
+    if (st != MARS_OK)
+        return st;
+    Workspace &w = I->ws;
+    const int B = d.B, kmax = d.kmax, ldt = d.ldt, ldr = d.ldr, ldm = d.ldm;
+    const std::vector<int> &pb = d.pb;
+    const bool bf16 = d.bf16;
+    const float gamma = d.gamma;
+    float *table = d.table;
+    int32_t *nlev = d.nlev;
+    void *cur = d.Ma, *nxt = d.Mb;
     // bf16 tile variant: the autotuner's choice for this shape (timed on the
     // first phase at the first level, which the sweep then recomputes)
     int variant = 0;
@@ -773,19 +818,7 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
                 break;
         }
     }
-    if ((st = ensure(w.spad, dense_spin_operand_bytes(*I, R))) != MARS_OK)
-        return st;
-    int8_t *spad = (int8_t *)w.spad.p;
-    if (bf16)
-        launch_bf16_round((const unsigned short *)cur, I->Np, N, R, I->Ke, spad, spins, m_final, s);
-    else
-        launch_dense_round((const float *)cur, ldm, N, R, I->Ke, spad, spins, m_final, s);
-    launch_dense_energy_i8(*I, spad, R, E, I->ws.partial.p, s);
-    launch_argmin(E, T0, runstat, R, N, I->wsum, res_dev, best_dev, s);
-    if (best_spins)
-        launch_gather_best(spad, I->Ke, best_dev, N, best_spins, s);
-    MARS_HIP(hipGetLastError());
-    return MARS_OK;
+    return dense_finish(I, d, cur, m_final, spins, E, best_spins, res_dev, best_dev, s);
 }
 
 static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const void *m0,
@@ -883,6 +916,159 @@ static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, ui
         *res = tmp;
     }
     return MARS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched BF16 solver: members advance together, one launch per phase
+// ---------------------------------------------------------------------------
+
+struct BatchMember {
+    Instance *I = nullptr;
+    DenseRun d;
+    int k = 0;  // next level
+    void *cur = nullptr, *nxt = nullptr;
+    int64_t tag = 0;
+    int8_t *best = nullptr;
+    mars_result *res_pinned = nullptr;
+    double *E = nullptr;
+    mars_result *res_dev = nullptr;
+    int32_t *best_dev = nullptr;
+};
+
+struct Batch {
+    int device = 0;
+    hipStream_t s = nullptr;
+    std::mutex mu;
+    std::vector<BatchMember> members;
+};
+
+static void release_member(BatchMember &m)
+{
+    std::lock_guard<std::mutex> lk(m.I->mu);
+    m.I->in_batch = false;
+}
+
+// last level done: per-run statistics, rounding, exact energies, best run,
+// copies to the caller's buffers
+static mars_status finish_member(Batch &b, BatchMember &m)
+{
+    launch_dense_runstat(m.d.R, m.d.nlev, (int64_t *)m.I->ws.runstat.p, b.s);
+    mars_status st = dense_finish(m.I, m.d, m.cur, nullptr, nullptr, m.E, m.best, m.res_dev, m.best_dev, b.s);
+    if (st == MARS_OK && m.res_pinned) {
+        hipError_t e = hipMemcpyAsync(m.res_pinned, m.res_dev, sizeof(mars_result), hipMemcpyDeviceToHost, b.s);
+        if (e != hipSuccess)
+            st = hip_error(e, "hipMemcpyAsync result");
+    }
+    if (st == MARS_OK)
+        st = order_end(m.I, b.s);
+    release_member(m);
+    return st;
+}
+
+static mars_status batch_add(Batch &b, Instance *I, int R, const mars_schedule *sc, uint64_t seed, int64_t tag,
+                             int8_t *best, mars_result *res_pinned)
+{
+    if (R < 1 || R >= (1 << 30))
+        return set_error(MARS_E_ARG, "runs must be in [1, 2^30)");
+    mars_status st = check_schedule(sc, I->kind);
+    if (st != MARS_OK)
+        return st;
+    if (I->kind != KIND_DENSE || sc->precision != MARS_BF16 || sc->max_sweeps != 1)
+        return set_error(MARS_E_UNSUPPORTED, "a batch holds dense instances solved in MARS_BF16 with max_sweeps 1");
+    if (I->device != b.device)
+        return set_error(MARS_E_UNSUPPORTED, "the instance lives on another device than the batch");
+    if ((int)b.members.size() >= kMaxBatchMembers)
+        return set_error(MARS_E_UNSUPPORTED, "the batch is full");
+    {
+        std::lock_guard<std::mutex> lk(I->mu);
+        if (I->in_batch)
+            return set_error(MARS_E_ARG, "the instance already belongs to a batch");
+        I->in_batch = true;
+    }
+    BatchMember m;
+    m.I = I;
+    m.tag = tag;
+    m.best = best;
+    m.res_pinned = res_pinned;
+    Workspace &w = I->ws;
+    auto fail = [&](mars_status e) {
+        release_member(m);
+        return e;
+    };
+    if ((st = order_begin(I, b.s)) != MARS_OK)
+        return fail(st);
+    if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK || (st = ensure(w.energies, sizeof(double) * R)) != MARS_OK ||
+        (st = ensure(w.partial, dense_energy_partial_bytes(*I, R))) != MARS_OK)
+        return fail(st);
+    m.E = (double *)w.energies.p;
+    m.res_dev = (mars_result *)w.result.p;
+    m.best_dev = (int32_t *)((char *)w.result.p + sizeof(mars_result) + 16);
+    if ((st = dense_setup(I, R, *sc, seed, nullptr, nullptr, m.d, b.s)) != MARS_OK)
+        return fail(st);
+    m.cur = m.d.Ma;
+    m.nxt = m.d.Mb;
+    b.members.push_back(m);
+    return MARS_OK;
+}
+
+static mars_status batch_step(Batch &b, int sweeps, int64_t *tags, int cap, int *n_fin)
+{
+    *n_fin = 0;
+    mars_status st = MARS_OK;
+    // members past their last level leave (as long as the tag array has room;
+    // the others leave at a later call and are not swept meanwhile)
+    auto retire = [&]() {
+        for (size_t i = 0; i < b.members.size() && *n_fin < cap;) {
+            BatchMember &m = b.members[i];
+            if (m.k < m.d.kmax) {
+                ++i;
+                continue;
+            }
+            mars_status e = finish_member(b, m);
+            if (e != MARS_OK && st == MARS_OK)
+                st = e;
+            tags[(*n_fin)++] = m.tag;
+            b.members.erase(b.members.begin() + (long)i);
+        }
+    };
+    retire();
+    Bf16GroupMember g[kMaxBatchMembers];
+    for (int sw = 0; sw < sweeps && st == MARS_OK; ++sw) {
+        int maxB = 0;
+        for (const BatchMember &m : b.members)
+            if (m.k < m.d.kmax)
+                maxB = std::max(maxB, m.d.B);
+        if (maxB == 0)
+            break;
+        for (int ph = 0; ph < maxB; ++ph) {
+            int n = 0;
+            for (const BatchMember &m : b.members) {
+                if (m.k >= m.d.kmax || ph >= m.d.B || m.d.pb[ph + 1] <= m.d.pb[ph])
+                    continue;
+                g[n].I = m.I;
+                g[n].Mold = (const unsigned short *)m.cur;
+                g[n].Mnew = (unsigned short *)m.nxt;
+                g[n].invT = m.d.table + (size_t)m.k * m.d.ldt;
+                g[n].R = m.d.R;
+                g[n].p0 = m.d.pb[ph];
+                g[n].p1 = m.d.pb[ph + 1];
+                g[n].gamma = m.d.gamma;
+                ++n;
+            }
+            if (n > 0) {
+                hipError_t e = launch_dense_phase_bf16_group(g, n, b.s);
+                if (e != hipSuccess)
+                    return hip_error(e, "grouped phase launch");
+            }
+        }
+        for (BatchMember &m : b.members)
+            if (m.k < m.d.kmax) {
+                std::swap(m.cur, m.nxt);
+                ++m.k;
+            }
+        retire();
+    }
+    return st;
 }
 
 }  // namespace mars
@@ -993,6 +1179,8 @@ mars_status mars_solve_ex(mars_instance *inst, int32_t runs, const mars_schedule
         return set_error(MARS_E_ARG, "instance is NULL");
     Instance *I = reinterpret_cast<Instance *>(inst);
     std::lock_guard<std::mutex> lk(I->mu);
+    if (I->in_batch)
+        return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     mars_status st = solve_impl(I, runs, sched, seed, m0, T0, m_final, spins, energies, best_spins,
                                 T0_used ? nullptr : res, s);
@@ -1016,6 +1204,8 @@ mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_sched
         return set_error(MARS_E_ARG, "instance is NULL");
     Instance *I = reinterpret_cast<Instance *>(inst);
     std::lock_guard<std::mutex> lk(I->mu);
+    if (I->in_batch)
+        return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     mars_status st = solve_impl(I, runs, sched, seed, m0, T0, m_final, spins, energies, best_spins, nullptr, s);
     if (st != MARS_OK || !res_pinned)
@@ -1031,6 +1221,8 @@ mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *s
         return set_error(MARS_E_ARG, "instance is NULL");
     Instance *I = reinterpret_cast<Instance *>(inst);
     std::lock_guard<std::mutex> lk(I->mu);
+    if (I->in_batch)
+        return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
     if (runs < 1)
         return set_error(MARS_E_ARG, "runs must be >= 1");
     mars_status st = check_schedule(sched, I->kind);
@@ -1076,6 +1268,8 @@ mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, dou
         return set_error(MARS_E_ARG, "need instance, spins, energies and R >= 1");
     Instance *I = reinterpret_cast<Instance *>(inst);
     std::lock_guard<std::mutex> lk(I->mu);
+    if (I->in_batch)
+        return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
     MARS_HIP(hipSetDevice(I->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     {
@@ -1095,6 +1289,68 @@ mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, dou
     }
     MARS_HIP(hipGetLastError());
     return order_end(I, s);
+}
+
+mars_status mars_batch_create(void *stream, mars_batch **out)
+{
+    if (!out)
+        return set_error(MARS_E_ARG, "out is NULL");
+    *out = nullptr;
+    Batch *b = new (std::nothrow) Batch;
+    if (!b)
+        return set_error(MARS_E_OOM, "batch");
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_error(e, "hipGetDevice");
+    }
+    b->s = reinterpret_cast<hipStream_t>(stream);
+    *out = reinterpret_cast<mars_batch *>(b);
+    return MARS_OK;
+}
+
+mars_status mars_batch_add(mars_batch *batch, mars_instance *inst, int32_t runs, const mars_schedule *sched,
+                           uint64_t seed, int64_t tag, int8_t *best_spins, mars_result *res_pinned)
+{
+    if (!batch || !inst || !sched)
+        return set_error(MARS_E_ARG, "need batch, instance and schedule");
+    Batch *b = reinterpret_cast<Batch *>(batch);
+    std::lock_guard<std::mutex> lk(b->mu);
+    MARS_HIP(hipSetDevice(b->device));
+    return batch_add(*b, reinterpret_cast<Instance *>(inst), runs, sched, seed, tag, best_spins, res_pinned);
+}
+
+mars_status mars_batch_step(mars_batch *batch, int32_t sweeps, int64_t *finished_tags, int32_t cap,
+                            int32_t *n_finished, int32_t *n_active)
+{
+    if (!batch || !n_finished || !n_active || sweeps < 0 || cap < 0 || (cap > 0 && !finished_tags))
+        return set_error(MARS_E_ARG, "need batch, counters, sweeps >= 0 and room for the tags");
+    Batch *b = reinterpret_cast<Batch *>(batch);
+    std::lock_guard<std::mutex> lk(b->mu);
+    MARS_HIP(hipSetDevice(b->device));
+    int nf = 0;
+    mars_status st = batch_step(*b, sweeps, finished_tags, cap, &nf);
+    *n_finished = nf;
+    *n_active = (int32_t)b->members.size();
+    return st;
+}
+
+void mars_batch_destroy(mars_batch *batch)
+{
+    if (!batch)
+        return;
+    Batch *b = reinterpret_cast<Batch *>(batch);
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        (void)hipSetDevice(b->device);
+        (void)hipStreamSynchronize(b->s);
+        for (BatchMember &m : b->members) {
+            (void)order_end(m.I, b->s);
+            release_member(m);
+        }
+        b->members.clear();
+    }
+    delete b;
 }
 
 const char *mars_status_str(mars_status s)

@@ -51,7 +51,8 @@ class Result(C.Structure):
 
 
 EXPORTS = ["mars_create", "mars_create_csr", "mars_create_lattice", "mars_destroy", "mars_describe", "mars_solve",
-           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_status_str", "mars_last_error"]
+           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_batch_create", "mars_batch_add",
+           "mars_batch_step", "mars_batch_destroy", "mars_status_str", "mars_last_error"]
 
 _lib = None
 _lock = threading.Lock()
@@ -78,12 +79,18 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(Result), vp]
         L.mars_solve_async.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mars_energy.argtypes = [vp, vp, i32, vp, vp]
+        L.mars_batch_create.argtypes = [vp, C.POINTER(vp)]
+        L.mars_batch_add.argtypes = [vp, vp, i32, C.POINTER(Schedule), u64, C.c_int64, vp, vp]
+        L.mars_batch_step.argtypes = [vp, i32, vp, i32, C.POINTER(i32), C.POINTER(i32)]
+        L.mars_batch_destroy.argtypes = [vp]
+        L.mars_batch_destroy.restype = None
         L.mars_status_str.argtypes = [C.c_int]
         L.mars_status_str.restype = C.c_char_p
         L.mars_last_error.argtypes = []
         L.mars_last_error.restype = C.c_char_p
         for f in ("mars_create", "mars_create_csr", "mars_create_lattice", "mars_describe", "mars_solve",
-                  "mars_solve_ex", "mars_solve_async", "mars_energy"):
+                  "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_batch_create", "mars_batch_add",
+                  "mars_batch_step"):
             getattr(L, f).restype = C.c_int
         _lib = L
         return L
@@ -272,6 +279,63 @@ class Instance:
         _check(load().mars_energy(self._h, _ptr(spins), int(spins.shape[0]), _ptr(E),
                                   C.c_void_p(torch.cuda.current_stream().cuda_stream)))
         return E
+
+
+class Batch:
+    """Batched BF16 solver (mars_batch_*): dense instances solved in MARS_BF16
+    with one sweep per level advance together on one stream, one launch per
+    phase for all members; members join and leave at sweep boundaries."""
+
+    MAX_MEMBERS = 16
+
+    def __init__(self, stream):
+        h = C.c_void_p()
+        _check(load().mars_batch_create(C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self._stream = stream
+        self._keep = {}  # tag -> (instance, outputs) held until the member finishes
+
+    def add(self, inst: Instance, runs: int, schedule, seed: int, tag: int, result_buf, *, want_best=True) -> dict:
+        """Join a solve of `inst`; `result_buf` (pinned uint8, >= sizeof(Result))
+        receives its summary when it finishes.  Returns the device outputs."""
+        import torch
+
+        if tag in self._keep:
+            raise ValueError("tag %d is already in the batch" % tag)
+        out = {}
+        if want_best:
+            out["best_spins"] = torch.empty(inst.N, dtype=torch.int8, device=torch.device("cuda", torch.cuda.current_device()))
+        s = make_schedule(schedule)
+        _check(load().mars_batch_add(self._h, inst._h, int(runs), C.byref(s), seed & (2**64 - 1), int(tag),
+                                     _ptr(out.get("best_spins")), result_buf.data_ptr()))
+        self._keep[tag] = (inst, out, result_buf)
+        return out
+
+    def step(self, sweeps: int, cap: int = 64):
+        """Advance every member by up to `sweeps` sweeps; returns (tags of the
+        members that finished, number still active)."""
+        tags = (C.c_int64 * max(cap, 1))()
+        nf, na = C.c_int32(), C.c_int32()
+        _check(load().mars_batch_step(self._h, int(sweeps), tags, int(cap), C.byref(nf), C.byref(na)))
+        done = [int(tags[i]) for i in range(nf.value)]
+        for t in done:
+            self._keep.pop(t, None)
+        return done, na.value
+
+    def __len__(self):
+        return len(self._keep)
+
+    def close(self):
+        if self._h:
+            load().mars_batch_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def status_str(status: int) -> str:
