@@ -127,7 +127,7 @@ def served(args):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    server = S.MarsServer(max_active=8, n_streams=4)
+    server = S.MarsServer(max_active=8, n_streams=4, batching=not args.no_batching)
 
     def make(rate):
         reqs = S.mixed_stream(args.requests, rate, seed=args.seed)
@@ -151,7 +151,8 @@ def served(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (dense) / f32 (sparse)",
         "data": "synthetic",
         "config": {"workload": "served", "description": DESCRIPTION["served"], "requests": st["requests"],
-                   "offered_rate_per_s": rate, "parallelism": "single GPU, concurrent streams"},
+                   "offered_rate_per_s": rate, "batching": not args.no_batching,
+                   "parallelism": "single GPU, concurrent streams"},
         "latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"]},
         "capacity": cap, "load": st, "roofline": None, "cpu_baseline": None,
     }
@@ -168,6 +169,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16", "fp16"],
                     help="override the workload's arithmetic form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="served workload: run every request alone on the stream pool")
     ap.add_argument("--requests", type=int, default=200, help="served workload: number of requests")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (to scale rocprofv3 byte counters)")

@@ -209,45 +209,45 @@ __device__ __forceinline__ void bf16_phase_tile(
 
     // epilogue: element (run = row, spin = column) of each 32 x 32 block; lane
     // l holds spin column l%32, register v holds run row 8*(v/4) + 4*(l/32) + v%4.
-    // Every operand of the update is loaded first, unconditionally (rows
-    // below the padded run count and columns below the padded dimension are
-    // in bounds), so the loads overlap instead of one round trip per element.
+    // Every operand of a row block's update is loaded first, unconditionally
+    // (rows below the padded run count and columns below the padded
+    // dimension are in bounds), so the loads overlap instead of one round
+    // trip per element.
     const bool damp = gamma != 1.0f;
-    float itv[MB][16], hv[NB];
-    unsigned short ov[MB][NB][16];
-#pragma unroll
-    for (int a = 0; a < MB; ++a)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int run = r0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
-            itv[a][v] = invT[run];
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                ov[a][b][v] = Mold[(size_t)run * ldk + i0 + wn * TN + b * 32 + li];
-        }
+    float hv[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
         hv[b] = hhalf ? hhalf[i0 + wn * TN + b * 32 + li] : 0.0f;
-    // The stores are unconditional too (a conditional store would make the
-    // wait counts conservative again): a row past R writes its old value
-    // back; a column past p1 belongs to a later phase of this sweep, which
-    // overwrites it before anything reads it (columns past N compute 0 from
-    // the zero padding of J and h).
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
+        float itv[16];
+        unsigned short ov[NB][16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int run = r0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
+            itv[v] = invT[run];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                ov[b][v] = Mold[(size_t)run * ldk + i0 + wn * TN + b * 32 + li];
+        }
+        // The stores are unconditional too (a conditional store would make
+        // the wait counts conservative again): a row past R writes its old
+        // value back; a column past p1 belongs to a later phase of this
+        // sweep, which overwrites it before anything reads it (columns past
+        // N compute 0 from the zero padding of J and h).
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int run = r0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * kh + (v & 3);
             const bool rok = run < R;
-            const float it = rok ? itv[a][v] : -1.0f;  // < 0: frozen (finished run or padding row)
+            const float it = rok ? itv[v] : -1.0f;  // < 0: frozen (finished run or padding row)
             float dl = 0.0f;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int spin = i0 + wn * TN + b * 32 + li;
-                const float old = bf16_to_float(ov[a][b][v]);
+                const float old = bf16_to_float(ov[b][v]);
                 const float th = bf16_form_tanh((acc[a][b][v] + hv[b]) * it);
                 const float upd = damp ? (1.0f - gamma) * old + gamma * th : th;
-                const unsigned short nb16 = it >= 0.0f ? float_to_bf16(upd) : ov[a][b][v];
+                const unsigned short nb16 = it >= 0.0f ? float_to_bf16(upd) : ov[b][v];
                 Mnew[(size_t)run * ldk + spin] = nb16;
                 const float dd = fabsf(bf16_to_float(nb16) - old);
                 dl = (rok && spin < p1) ? fmaxf(dl, dd) : dl;

@@ -9,6 +9,13 @@ their slot and memory; their device buffers are released when the GPU is idle
 or when the memory is needed (releasing device memory synchronises the
 device).
 
+Dense requests in the BF16 form that are too small to fill the GPU on their
+own (fewer 128 x 128 output tiles per update phase than the chip has compute
+units) join a batch instead (``mars_batch_*``): every update phase of all
+batch members is one launch, and members join and leave between sweeps.
+Larger requests run alone on the stream pool, where they fill the GPU
+anyway, and do not hold small members back to their pace.
+
 Every solve is independent and deterministic (counter-based draws, fixed
 reduction orders), so a request's result is the same whether it runs alone
 or in the mix; ``tests/test_gpu_serve.py`` checks that bit for bit.
@@ -120,6 +127,24 @@ def footprint_bytes(req: Request) -> int:
     return int((inst_b + work) * 1.05) + (1 << 20)
 
 
+BATCH_TILES = 256  # one tile per compute unit
+
+
+def phase_tiles(req: Request) -> int:
+    """Output tiles (128 runs x 128 spins) of one update phase of a dense solve."""
+    sc = req.schedule
+    phases = 1 if sc.update == "jacobi" else max(1, min(sc.phases, req.N))
+    width = -(-req.N // phases)
+    return -(-req.runs // 128) * -(-width // 128)
+
+
+def batchable(req: Request, tiles: int = BATCH_TILES) -> bool:
+    """A request that the batched BF16 solver takes: dense, BF16 form, one
+    sweep per level, and too small to fill the GPU alone."""
+    sc = req.schedule
+    return req.dense and sc.precision == "bf16" and sc.max_sweeps == 1 and phase_tiles(req) < tiles
+
+
 class Scheduler:
     """Admission policy: FIFO by arrival, admit while a slot and memory are free.
 
@@ -140,14 +165,17 @@ class Scheduler:
             return
         heapq.heappush(self.queue, (req.arrival, req.rid, req))
 
-    def admissible(self, now: float):
-        """Pop the requests that can start now (arrived, slot and memory free)."""
+    def admissible(self, now: float, accept=None):
+        """Pop the requests that can start now (arrived, slot and memory free,
+        and `accept(req)` true if given: the executor's own slot classes)."""
         out = []
         while self.queue and self.queue[0][0] <= now and self.active < self.max_active:
             req = self.queue[0][2]
             fp = footprint_bytes(req)
             if self.in_use + fp > self.budget:
                 break  # FIFO: wait for memory rather than overtake
+            if accept is not None and not accept(req):
+                break  # FIFO: wait for a slot of the request's class
             heapq.heappop(self.queue)
             self.in_use += fp
             self.active += 1
@@ -177,7 +205,8 @@ class Scheduler:
 class MarsServer:
     """Runs a stream of requests with continuous batching on the current GPU."""
 
-    def __init__(self, hbm_budget: int | None = None, max_active: int = 8, n_streams: int = 4):
+    def __init__(self, hbm_budget: int | None = None, max_active: int = 8, n_streams: int = 4, batching: bool = True,
+                 batch_sweeps: int = 8):
         import torch
 
         from . import mars as M
@@ -191,69 +220,114 @@ class MarsServer:
         self.max_active = max_active
         # default-priority streams (torch creates them non-blocking)
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.batching = batching
+        self.batch_sweeps = int(batch_sweeps)
+        self.batch_stream = torch.cuda.Stream() if batching else None
 
     def run(self, requests, time_scale: float = 1.0, verbose: bool = False):
         """Serve `requests` (arrival times in seconds, scaled by time_scale);
         returns (completions, stats)."""
         torch, M = self.torch, self.M
-        sched = Scheduler(self.hbm_budget, self.max_active)
+        cap = self.M.Batch.MAX_MEMBERS if self.batching else 0
+        # the batch's members have slots of their own beside the stream pool's
+        sched = Scheduler(self.hbm_budget, self.max_active + cap)
         for r in requests:
             sched.submit(r)
-        running = []  # dicts: req, inst, event, outs, buf, fp, admitted, stream
+        batch = M.Batch(self.batch_stream) if self.batching else None
+        inflight = []  # events after the batch's recent steps (at most two queued)
+        running = []  # dicts: req, inst, event, outs, buf, fp, admitted, stream (-1: batch)
+        by_tag = {}
         graveyard = []  # finished instances awaiting release (frees synchronise the device)
         done = []
         stream_load = [0] * len(self.streams)
-        peak_running = 0
+        peak_running = peak_batch = 0
         t0 = time.perf_counter()
-        while sched.queue or running:
-            now = (time.perf_counter() - t0) / time_scale
-            progressed = False
-            # retire finished requests
-            still = []
-            for job in running:
-                if job["event"].query():
-                    res = M.Instance.read_result(job["buf"])
-                    best = job["outs"]["best_spins"].cpu().numpy()
-                    fin = (time.perf_counter() - t0) / time_scale
-                    done.append(Completion(job["req"].rid, res, best, job["req"].arrival, job["admitted"], fin,
-                                           job["fp"]))
-                    graveyard.append((job["inst"], job["fp"]))
-                    sched.finish()
-                    stream_load[job["stream"]] -= 1
+        try:
+            while sched.queue or running:
+                now = (time.perf_counter() - t0) / time_scale
+                progressed = False
+                # retire finished requests
+                still = []
+                for job in running:
+                    if job["event"] is not None and job["event"].query():
+                        res = M.Instance.read_result(job["buf"])
+                        best = job["outs"]["best_spins"].cpu().numpy()
+                        fin = (time.perf_counter() - t0) / time_scale
+                        done.append(Completion(job["req"].rid, res, best, job["req"].arrival, job["admitted"], fin,
+                                               job["fp"]))
+                        graveyard.append((job["inst"], job["fp"]))
+                        sched.finish()
+                        if job["stream"] >= 0:
+                            stream_load[job["stream"]] -= 1
+                        progressed = True
+                    else:
+                        still.append(job)
+                running = still
+                # release device memory only while nothing runs: a free synchronises
+                # the device, which would stall the running solves
+                if graveyard and not running:
+                    for inst, fp in graveyard:
+                        inst.close()
+                        sched.free(fp)
+                    graveyard = []
                     progressed = True
-                else:
-                    still.append(job)
-            running = still
-            # release device memory only while nothing runs: a free synchronises
-            # the device, which would stall the running solves
-            if graveyard and not running:
-                for inst, fp in graveyard:
-                    inst.close()
-                    sched.free(fp)
-                graveyard = []
-                progressed = True
-            # admit
-            for req, fp in sched.admissible(now):
-                k = int(np.argmin(stream_load))
-                stream = self.streams[k]
-                inst = M.Instance.from_inputs(req.materialize())
-                buf = torch.empty(256, dtype=torch.uint8, pin_memory=True)
-                outs = inst.solve_async(req.runs, req.schedule, req.seed, buf, stream=stream)
-                ev = torch.cuda.Event()
-                ev.record(stream)
-                stream_load[k] += 1
-                running.append({"req": req, "inst": inst, "event": ev, "outs": outs, "buf": buf, "fp": fp,
-                                "admitted": (time.perf_counter() - t0) / time_scale, "stream": k})
-                if verbose:
-                    print("admit", req.rid, "N", req.N, "runs", req.runs, "stream", k, flush=True)
-                progressed = True
-            peak_running = max(peak_running, len(running))
-            if not progressed:
-                nxt = sched.next_arrival()
-                wait = 2e-4
-                if nxt is not None and not running:
-                    wait = max(0.0, min(0.05, (nxt - now) * time_scale))
-                time.sleep(wait)
+                # admit: batch members up to the batch's capacity, other
+                # requests up to max_active on the stream pool
+                room = {"batch": cap - len(batch) if batch is not None else 0,
+                        "solo": self.max_active - sum(stream_load)}
+
+                def accept(req):
+                    cls = "batch" if room["batch"] > 0 and batchable(req) else "solo"
+                    if room[cls] <= 0:
+                        return False
+                    room[cls] -= 1
+                    return True
+
+                for req, fp in sched.admissible(now, accept):
+                    inst = M.Instance.from_inputs(req.materialize())
+                    buf = torch.empty(256, dtype=torch.uint8, pin_memory=True)
+                    job = {"req": req, "inst": inst, "event": None, "buf": buf, "fp": fp,
+                           "admitted": (time.perf_counter() - t0) / time_scale}
+                    if batch is not None and len(batch) < cap and batchable(req):
+                        with torch.cuda.stream(self.batch_stream):
+                            job["outs"] = batch.add(inst, req.runs, req.schedule, req.seed, req.rid, buf)
+                        job["stream"] = -1
+                        by_tag[req.rid] = job
+                    else:
+                        k = int(np.argmin(stream_load))
+                        stream = self.streams[k]
+                        job["outs"] = inst.solve_async(req.runs, req.schedule, req.seed, buf, stream=stream)
+                        ev = torch.cuda.Event()
+                        ev.record(stream)
+                        job["event"] = ev
+                        job["stream"] = k
+                        stream_load[k] += 1
+                    running.append(job)
+                    if verbose:
+                        print("admit", req.rid, "N", req.N, "runs", req.runs, "stream", job["stream"], flush=True)
+                    progressed = True
+                # advance the batch, keeping at most two steps queued ahead of the GPU
+                while inflight and inflight[0].query():
+                    inflight.pop(0)
+                if batch is not None and len(batch) and len(inflight) < 2:
+                    peak_batch = max(peak_batch, len(batch))
+                    fin_tags, _ = batch.step(self.batch_sweeps, cap=cap)
+                    ev = torch.cuda.Event()
+                    ev.record(self.batch_stream)
+                    inflight.append(ev)
+                    for t in fin_tags:
+                        by_tag.pop(t)["event"] = ev
+                    progressed = True
+                peak_running = max(peak_running, len(running))
+                if not progressed:
+                    nxt = sched.next_arrival()
+                    wait = 2e-4
+                    if nxt is not None and not running:
+                        wait = max(0.0, min(0.05, (nxt - now) * time_scale))
+                    time.sleep(wait)
+        finally:
+            if batch is not None:
+                batch.close()
         for inst, fp in graveyard:
             inst.close()
             sched.free(fp)
@@ -261,7 +335,7 @@ class MarsServer:
         lat = np.array([c.latency for c in done]) if done else np.zeros(1)
         updates = sum(int(c.result["spin_updates"]) for c in done)
         stats = {"requests": len(done), "rejected": len(sched.rejected), "makespan_s": makespan,
-                 "peak_concurrent": peak_running,
+                 "peak_concurrent": peak_running, "peak_batch": peak_batch,
                  "spin_updates": updates, "spin_updates_per_s": updates / makespan if makespan > 0 else 0.0,
                  "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
                  "latency_p99_ms": float(np.percentile(lat, 99) * 1e3)}

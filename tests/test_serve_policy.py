@@ -78,3 +78,33 @@ def test_mixed_stream_shape():
     assert sum(kinds) == 100
     gaps = np.diff([r.arrival for r in reqs])
     assert np.all(gaps >= 0) and abs(gaps.mean() - 0.1) < 0.03
+
+
+def test_batchable_requests():
+    """Only dense BF16 one-sweep-per-level requests smaller than one tile per
+    compute unit per phase join the batch."""
+    sch = I.Schedule(phases=2, precision="bf16")
+    small = S.Request(0, S.InstanceSpec("sk", 1000, 1), 1024, sch, seed=1)
+    assert S.phase_tiles(small) == 8 * 4 and S.batchable(small)
+    big = S.Request(1, S.InstanceSpec("sk", 10000, 1), 4096, sch, seed=1)
+    assert S.phase_tiles(big) == 32 * 40 and not S.batchable(big)
+    assert not S.batchable(S.Request(2, S.InstanceSpec("sk", 1000, 1), 1024, sch.replace(precision="fp32"), seed=1))
+    assert not S.batchable(S.Request(3, S.InstanceSpec("er", 1000, 1), 1024, sch, seed=1))
+    jac = S.Request(4, S.InstanceSpec("sk", 1000, 1), 1024, sch.replace(update="jacobi"), seed=1)
+    assert S.phase_tiles(jac) == 8 * 8
+    slow = S.Request(5, S.InstanceSpec("sk", 1000, 1), 1024,
+                     sch.replace(kind="linear", max_sweeps=10, c_step=0.1), seed=1)
+    assert not S.batchable(slow)
+
+
+def test_accept_predicate_keeps_fifo():
+    """A request refused by the executor's slot classes blocks the queue
+    behind it (first come, first served) without being lost."""
+    reqs = _reqs(6, seed=3, rate=0.0)
+    sched = S.Scheduler(1 << 40, 10)
+    for r in reqs:
+        sched.submit(r)
+    first = sched.admissible(1.0, accept=lambda r: r.rid < 2)
+    assert [r.rid for r, _ in first] == [0, 1] and sched.active == 2
+    rest = sched.admissible(1.0)
+    assert [r.rid for r, _ in rest] == [2, 3, 4, 5]
