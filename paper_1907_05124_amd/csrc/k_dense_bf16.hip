@@ -13,13 +13,14 @@
 
 namespace mars {
 
-// Tile variants of the phase kernel (register prefetch ring of two slabs;
-// 64- or 128-deep slabs, both visiting K in the same order).  Every variant reduces each output
-// element over K in the same order (64-deep slabs, one wave per 32 x 32
-// block), so all of them produce bitwise identical results; they differ in
-// how many workgroups a phase yields.  128 x 128 x 16 waves is the fastest on
-// the SK N=2000 x 4096-run shape; smaller tiles fill the GPU on small
-// instances.
+// Tile variants of the phase kernel (register prefetch ring of two slabs,
+// one wave per 32 x 32 block).  Every variant reduces each output element
+// over K in the same order (16-deep MFMA steps in increasing k, whatever the
+// slab depth), so all of them produce bitwise identical results; they differ
+// in how many workgroups a phase yields and how many barriers it takes.  128 x 128 x 16 waves with 128-deep
+// slabs (half the barriers of 64-deep ones) is the fastest on the SK N=2000 x
+// 4096-run shape and the default before the tuner has decided; smaller tiles
+// fill the GPU on small instances.
 typedef void (*Bf16PhaseFn)(const unsigned short *, int, const unsigned short *, unsigned short *, int, int, int,
                             int, int, int, int, const float *, const float *, float, uint32_t *);
 // fn_aligned: the phase starts at a multiple of 8 spins (no 8-spin chunk
@@ -34,11 +35,11 @@ struct Bf16Variant {
             k_dense_phase_bf16<BM, BN, WM, WN, PF, BK, true>                                    \
     }
 static const Bf16Variant kBf16Variants[] = {
-    BF16_VARIANT(128, 128, 4, 4, 2, 64),
+    BF16_VARIANT(128, 128, 4, 4, 2, 128),
     BF16_VARIANT(64, 128, 2, 4, 2, 64),
     BF16_VARIANT(128, 64, 4, 2, 2, 64),
     BF16_VARIANT(64, 64, 2, 2, 2, 64),
-    BF16_VARIANT(128, 128, 4, 4, 2, 128),
+    BF16_VARIANT(128, 128, 4, 4, 2, 64),
 };
 #undef BF16_VARIANT
 constexpr int kNumBf16Variants = sizeof(kBf16Variants) / sizeof(kBf16Variants[0]);

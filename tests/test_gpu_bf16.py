@@ -89,9 +89,9 @@ def test_bf16_tile_variants_bitwise(tile, monkeypatch):
     assert np.array_equal(a["energies"].cpu().numpy(), b["energies"].cpu().numpy())
 
 
-@pytest.mark.parametrize("tile", ["1", "3", "4"])
+@pytest.mark.parametrize("tile", ["1", "2", "3", "4"])
 def test_bf16_one_level_small_tiles(tile, monkeypatch):
-    """One level on a forced small-tile variant, same bar as the default tile."""
+    """One level on each forced non-default variant, same bar as the default tile."""
     monkeypatch.setenv("MARS_BF16_TILE", tile)
     test_bf16_one_level(517, 129, 3, 0.4)
 
