@@ -12,7 +12,8 @@
 //  * The threads of a wave cover consecutive slots, so their entry reads
 //    (column j of a slice) are consecutive words.
 //  * Missing entries of a slice point at the all-zero row nslot, so every
-//    lane of a slice runs the same number of terms.
+//    lane of a slice runs the same number of terms; slice widths are whole
+//    groups of SELL_W entries, read together before their terms are summed.
 //  * With +-1 weights the weight is rebuilt as +-1.0f from the entry's sign
 //    bit (one bit operation) instead of an integer-to-float conversion.
 #include <algorithm>
@@ -121,15 +122,21 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                     phi[e] = 0;
-#pragma unroll 4
-                for (int j = 0; j < w; ++j) {
-                    const uint32_t cb = cp[j * SELL_H];
-                    const C wt = entry_weight<C, UNIT>(cb);
-                    const Pack<S, VEC> t =
-                        lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((cb & 0xffffffu) << lgs)));
+                // w is a multiple of SELL_W: whole groups, no remainder loop
+                for (int j = 0; j < w; j += SELL_W) {
+                    uint32_t cb[SELL_W];
 #pragma unroll
-                    for (int e = 0; e < VEC; ++e)
-                        phi[e] += wt * LStore<S>::ld(t.v[e]);
+                    for (int u = 0; u < SELL_W; ++u)
+                        cb[u] = cp[(j + u) * SELL_H];
+#pragma unroll
+                    for (int u = 0; u < SELL_W; ++u) {
+                        const C wt = entry_weight<C, UNIT>(cb[u]);
+                        const Pack<S, VEC> t =
+                            lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((cb[u] & 0xffffffu) << lgs)));
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            phi[e] += wt * LStore<S>::ld(t.v[e]);
+                    }
                 }
                 if (HAS_H) {
                     C hh;

@@ -16,6 +16,7 @@ namespace mars {
 enum Kind { KIND_DENSE = 0, KIND_CSR = 1, KIND_LATTICE = 2 };
 
 constexpr int SELL_H = 8;  // slots per slice of the sparse solver's layout
+constexpr int SELL_W = 4;  // slice widths are padded to a multiple of this
 constexpr size_t RUN_AREA_MAX = 96;  // LDS bytes reserved per run for its level state
 
 // Device buffer owned by an instance; grows on demand, freed on destroy.
@@ -69,7 +70,8 @@ struct Instance {
     // sliced-ELL copy used by the solver: vertices relabelled into slots,
     // colour class by colour class, each class sorted by degree (descending)
     // and padded to a multiple of SELL_H slots; slice s (SELL_H consecutive
-    // slots) holds width w_s = its largest degree and entries
+    // slots) holds width w_s = its largest degree rounded up to a multiple
+    // of SELL_W and entries
     // colsell[off_s + j * SELL_H + (slot % SELL_H)], j < w_s, each
     // (neighbour slot) | (uint8(weight) << 24); a missing entry names the
     // all-zero row nslot with weight +1

@@ -481,6 +481,7 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
             if (v >= 0)
                 w = std::max(w, rowptr[v + 1] - rowptr[v]);
         }
+        w = (w + SELL_W - 1) / SELL_W * SELL_W;  // whole groups of SELL_W entries
         meta[2 * sl] = (int32_t)total;
         meta[2 * sl + 1] = w;
         total += (size_t)w * SELL_H;
