@@ -113,11 +113,19 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
             const int sn = JAC ? ns : a.cls[2 * c + 1];
             const unsigned char *mb = reinterpret_cast<const unsigned char *>(m) + q0 * sizeof(S);
             unsigned char *wb = reinterpret_cast<unsigned char *>(JAC ? m2 : m) + q0 * sizeof(S);
+            // the slice record (offset, width) of the thread's next slot is
+            // read while the current one is computed (index clamped to the
+            // class's last slot: in bounds, unused past the end)
+            const int2 *rec = reinterpret_cast<const int2 *>(meta);
+            const unsigned last = (unsigned)min(sb + max(sn, 1) - 1, ns - 1);
+            int2 rc = rec[min((unsigned)(sb + tq), last) / SELL_H];
             for (int it = tq; it < sn; it += Tq) {
                 const int slot = sb + it;
-                const int off = meta[2 * (slot / SELL_H)];
-                const int w = meta[2 * (slot / SELL_H) + 1];
-                const uint32_t *cp = colsell + off + (slot % SELL_H);
+                const int2 rn = rec[min((unsigned)(slot + Tq), last) / SELL_H];
+                const int off = rc.x;
+                const int w = rc.y;
+                rc = rn;
+                const uint32_t *cp = colsell + off + ((unsigned)slot % SELL_H);
                 C phi[VEC];
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
