@@ -19,7 +19,15 @@
 
 namespace mars {
 
-template <typename S, int VEC, int DIM, bool JAC, bool TRACKD, bool HAS_H>
+// keeps a value opaque to the optimiser, so that byte offsets stay plain
+// additions instead of being re-derived from site indices at every use
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    __asm__ volatile("" : "+v"(x));
+    return x;
+}
+
+template <typename S, int VEC, int DIM, bool JAC, bool TRACKD, bool HAS_H, bool DAMP>
 __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
 {
     typedef typename LStore<S>::C C;
@@ -63,7 +71,6 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
         dq[q] = 0;
     }
     const C g = (C)a.damping;
-    const bool damp = a.damping != 1.0;
 
     const int L0 = a.L0, L1 = a.L1, L2 = a.L2;
     const int plane = L0 * L1, vol = plane * L2;
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
         // o*: byte offsets of its neighbours along +x, -x, +y, -y, +z, -z
         auto site = [&](int v, uint32_t vb, uint32_t oxp, uint32_t oxm, uint32_t oyp, uint32_t oym, uint32_t ozp,
                         uint32_t ozm) {
-            const uint32_t b = bonds[v];
+            const uint32_t b = bonds[(unsigned)v];
             C phi[VEC];
             if constexpr (sizeof(S) == 2 && VEC == 2) {
                 // packed pair of fp16 runs: one 32-bit read per neighbour; each
@@ -193,7 +200,7 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
             for (int e = 0; e < VEC; ++e) {
                 const C th = l_tanh(l_apply(phi[e], scale[e]));
                 const C o = LStore<S>::ld(old.v[e]);
-                C n = damp ? ((C)1 - g) * o + g * th : th;
+                C n = DAMP ? ((C)1 - g) * o + g * th : th;
                 n = done[e] ? o : n;  // a finished run keeps its state
                 nw.v[e] = done[e] ? old.v[e] : LStore<S>::st(n);
                 const C dd = n > o ? n - o : o - n;
@@ -202,7 +209,28 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
             lds_put<S, VEC>(reinterpret_cast<S *>(wb + vb), nw);
         };
         for (int c = 0; c < (JAC ? 1 : 2); ++c) {
-            if (cols) {
+            if (cols && !JAC && (kz & 1) == 0) {
+                // even walk step: the thread's x parity is fixed for the whole
+                // walk, so its site, x and y offsets are constants; only the
+                // first and last planes of the lattice wrap along z
+                const int p = (c + cy + cz0) & 1;
+                int v = L0 * (cy + L1 * cz0) + 2 * xh + p;
+                uint32_t vb = ob(v);
+                const int dv = kz * plane;
+                const uint32_t dvb = opaque(ob(dv));
+                const uint32_t xp = opaque(p ? oxp1 : oxp0), xm = opaque(p ? oxm1 : oxm0);
+                const uint32_t yp = opaque(cyp), ym = opaque(cym);
+                const uint32_t zp = opaque(ob(plane)), zm = opaque(ob(-plane));
+                for (int z = cz0; z < L2; z += kz, v += dv, vb += dvb) {
+                    if (z > 0 && z + 1 < L2) {
+                        site(v, vb, xp, xm, yp, ym, zp, zm);
+                    } else {
+                        const uint32_t ozp = z + 1 < L2 ? zp : ob(plane - vol);
+                        const uint32_t ozm = z > 0 ? zm : ob(vol - plane);
+                        site(v, vb, xp, xm, yp, ym, ozp, ozm);
+                    }
+                }
+            } else if (cols) {
                 // site and byte offset carried along the column
                 int v0 = L0 * (cy + L1 * cz0) + 2 * xh;
                 uint32_t vb0 = ob(v0);
@@ -281,18 +309,22 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
                 rsl[q0 + e].write_stats(a.runstat, run0 + e);
 }
 
-template <typename S, int VEC, int DIM, bool HAS_H>
+template <typename S, int VEC, int DIM, bool HAS_H, bool DAMP>
 static void (*lat_pick3(bool jac, bool trackd))(GraphArgs, int)
 {
     if (jac)
-        return trackd ? k_lattice_solve<S, VEC, DIM, true, true, HAS_H> : k_lattice_solve<S, VEC, DIM, true, false, HAS_H>;
-    return trackd ? k_lattice_solve<S, VEC, DIM, false, true, HAS_H> : k_lattice_solve<S, VEC, DIM, false, false, HAS_H>;
+        return trackd ? k_lattice_solve<S, VEC, DIM, true, true, HAS_H, DAMP>
+                      : k_lattice_solve<S, VEC, DIM, true, false, HAS_H, DAMP>;
+    return trackd ? k_lattice_solve<S, VEC, DIM, false, true, HAS_H, DAMP>
+                  : k_lattice_solve<S, VEC, DIM, false, false, HAS_H, DAMP>;
 }
 
 template <typename S, int VEC, bool HAS_H>
-static void (*lat_pick(int dim, bool jac, bool trackd))(GraphArgs, int)
+static void (*lat_pick(int dim, bool jac, bool trackd, bool damp))(GraphArgs, int)
 {
-    return dim == 3 ? lat_pick3<S, VEC, 3, HAS_H>(jac, trackd) : lat_pick3<S, VEC, 2, HAS_H>(jac, trackd);
+    if (damp)
+        return dim == 3 ? lat_pick3<S, VEC, 3, HAS_H, true>(jac, trackd) : lat_pick3<S, VEC, 2, HAS_H, true>(jac, trackd);
+    return dim == 3 ? lat_pick3<S, VEC, 3, HAS_H, false>(jac, trackd) : lat_pick3<S, VEC, 2, HAS_H, false>(jac, trackd);
 }
 
 template <typename S, int VEC>
@@ -300,8 +332,9 @@ static hipError_t lat_launch(const GraphArgs &a, int lg_rpw, bool jac, bool trac
                              size_t lds, hipStream_t s)
 {
     const bool has_h = a.hhalf32 != nullptr;
-    void (*fn)(GraphArgs, int) =
-        has_h ? lat_pick<S, VEC, true>(a.dim, jac, trackd) : lat_pick<S, VEC, false>(a.dim, jac, trackd);
+    const bool damp = a.damping != 1.0;
+    void (*fn)(GraphArgs, int) = has_h ? lat_pick<S, VEC, true>(a.dim, jac, trackd, damp)
+                                       : lat_pick<S, VEC, false>(a.dim, jac, trackd, damp);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
