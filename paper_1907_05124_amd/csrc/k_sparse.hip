@@ -35,7 +35,7 @@ __device__ inline C entry_weight(uint32_t cb)
         return (C)((int32_t)cb >> 24);
 }
 
-template <typename S, int VEC, bool JAC, bool TRACKD, bool HAS_H, bool UNIT>
+template <typename S, int VEC, bool JAC, bool TRACKD, bool HAS_H, bool UNIT, bool DAMP>
 __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
 {
     typedef typename LStore<S>::C C;
@@ -80,7 +80,6 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
         dq[q] = 0;
     }
     const C g = (C)a.damping;
-    const bool damp = a.damping != 1.0;
     int lgs = lg_rpw;  // log2 of the byte stride of one slot's row
     for (int sz = (int)sizeof(S); sz > 1; sz >>= 1)
         ++lgs;
@@ -163,7 +162,7 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                 for (int e = 0; e < VEC; ++e) {
                     const C th = l_tanh(l_apply(phi[e], scale[e]));
                     const C o = LStore<S>::ld(old.v[e]);
-                    C n = damp ? ((C)1 - g) * o + g * th : th;
+                    C n = DAMP ? ((C)1 - g) * o + g * th : th;
                     n = done[e] ? o : n;  // a finished run keeps its state
                     nw.v[e] = done[e] ? old.v[e] : LStore<S>::st(n);
                     const C dd = n > o ? n - o : o - n;
@@ -221,20 +220,28 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
 
 typedef void (*SparseFn)(GraphArgs, int);
 
-template <typename S, int VEC, bool HAS_H, bool UNIT>
+template <typename S, int VEC, bool HAS_H, bool UNIT, bool DAMP>
 static SparseFn sp_pick(bool jac, bool trackd)
 {
     if (jac)
-        return trackd ? k_sparse_solve<S, VEC, true, true, HAS_H, UNIT> : k_sparse_solve<S, VEC, true, false, HAS_H, UNIT>;
-    return trackd ? k_sparse_solve<S, VEC, false, true, HAS_H, UNIT> : k_sparse_solve<S, VEC, false, false, HAS_H, UNIT>;
+        return trackd ? k_sparse_solve<S, VEC, true, true, HAS_H, UNIT, DAMP>
+                      : k_sparse_solve<S, VEC, true, false, HAS_H, UNIT, DAMP>;
+    return trackd ? k_sparse_solve<S, VEC, false, true, HAS_H, UNIT, DAMP>
+                  : k_sparse_solve<S, VEC, false, false, HAS_H, UNIT, DAMP>;
 }
 
-template <typename S, int VEC>
+template <typename S, int VEC, bool DAMP>
 static SparseFn sp_pick_hu(bool has_h, bool unit, bool jac, bool trackd)
 {
     if (has_h)
-        return unit ? sp_pick<S, VEC, true, true>(jac, trackd) : sp_pick<S, VEC, true, false>(jac, trackd);
-    return unit ? sp_pick<S, VEC, false, true>(jac, trackd) : sp_pick<S, VEC, false, false>(jac, trackd);
+        return unit ? sp_pick<S, VEC, true, true, DAMP>(jac, trackd) : sp_pick<S, VEC, true, false, DAMP>(jac, trackd);
+    return unit ? sp_pick<S, VEC, false, true, DAMP>(jac, trackd) : sp_pick<S, VEC, false, false, DAMP>(jac, trackd);
+}
+
+template <typename S, int VEC>
+static SparseFn sp_pick_d(bool damp, bool has_h, bool unit, bool jac, bool trackd)
+{
+    return damp ? sp_pick_hu<S, VEC, true>(has_h, unit, jac, trackd) : sp_pick_hu<S, VEC, false>(has_h, unit, jac, trackd);
 }
 
 // esz: bytes per stored magnetisation; rpw: runs per workgroup (power of two);
@@ -246,17 +253,18 @@ hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int
     while ((1 << lg) < rpw)
         ++lg;
     const bool has_h = a.hhalf32 != nullptr;
+    const bool damp = a.damping != 1.0;
     SparseFn fn;
     if (esz == 8)
-        fn = sp_pick_hu<double, 1>(has_h, unit, jac, trackd);
+        fn = sp_pick_d<double, 1>(damp, has_h, unit, jac, trackd);
     else if (esz == 4)
-        fn = vec == 4   ? sp_pick_hu<float, 4>(has_h, unit, jac, trackd)
-             : vec == 2 ? sp_pick_hu<float, 2>(has_h, unit, jac, trackd)
-                        : sp_pick_hu<float, 1>(has_h, unit, jac, trackd);
+        fn = vec == 4   ? sp_pick_d<float, 4>(damp, has_h, unit, jac, trackd)
+             : vec == 2 ? sp_pick_d<float, 2>(damp, has_h, unit, jac, trackd)
+                        : sp_pick_d<float, 1>(damp, has_h, unit, jac, trackd);
     else
-        fn = vec == 4   ? sp_pick_hu<_Float16, 4>(has_h, unit, jac, trackd)
-             : vec == 2 ? sp_pick_hu<_Float16, 2>(has_h, unit, jac, trackd)
-                        : sp_pick_hu<_Float16, 1>(has_h, unit, jac, trackd);
+        fn = vec == 4   ? sp_pick_d<_Float16, 4>(damp, has_h, unit, jac, trackd)
+             : vec == 2 ? sp_pick_d<_Float16, 2>(damp, has_h, unit, jac, trackd)
+                        : sp_pick_d<_Float16, 1>(damp, has_h, unit, jac, trackd);
     const size_t rows = (size_t)a.nslot + 1;
     const size_t lds = ((rows * rpw * esz * (jac ? 2 : 1) + 15) & ~(size_t)15) + rpw * RUN_AREA_BYTES;
     const int nq = rpw / (esz == 8 ? 1 : vec);

@@ -33,6 +33,10 @@ CASES = {
     "ea2d_6x4": lambda: I.lattice_instance((6, 4), 2),
     "ea3d_8": lambda: I.lattice_instance((8, 8, 8), 3),
     "ea3d_4x6x8": lambda: I.lattice_instance((4, 6, 8), 4),
+    # 16^3: each thread walks two planes (interior and wrapping ones);
+    # 20x20x8: the walk step is odd, so the x parity alternates along it
+    "ea3d_16": lambda: I.lattice_instance((16, 16, 16), 9),
+    "ea3d_20x20x8": lambda: I.lattice_instance((20, 20, 8), 10),
     "er_pm1": lambda: I.er_instance(800, 5, p=0.06, weights="pm1"),
     "er_unit": lambda: I.er_instance(300, 6, p=0.05, weights="unit"),
     "er_field": lambda: _with_field(I.er_instance(200, 7, p=0.05, weights="pm1"), 0.4),
@@ -60,7 +64,25 @@ def test_one_level_parity(case, precision, tol):
     assert err <= tol, err
 
 
-RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "ea3d_8", "ea2d_6x4", "lat_field"]
+@pytest.mark.parametrize("case", ["ea3d_16", "ea3d_20x20x8", "ea2d_16", "er_pm1", "er_field", "lat_field"])
+@pytest.mark.parametrize("update", ["phased", "jacobi"])
+def test_damped_parity(case, update):
+    """Damped update m <- (1 - g) m + g tanh(...) with g = 0.5 (the damped
+    kernels are separate instantiations): five fp32 levels within 1e-5 of the
+    oracle."""
+    M = _mars()
+    inst = CASES[case]()
+    sch = _rel_sched(inst, precision="fp32", update=update, damping=0.5, level_count=5)
+    R = 200
+    announce("graph damped", case, update, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 29, want_m=True)
+    ref = O.solve(inst, R, sch, 29, run_count=R)
+    err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
+    assert err <= 1e-5, err
+
+
+RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "ea3d_8", "ea3d_16", "ea2d_6x4", "lat_field"]
 
 
 @pytest.mark.parametrize("case", RUN_BLOCK_CASES)
