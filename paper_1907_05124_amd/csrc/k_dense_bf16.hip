@@ -181,36 +181,74 @@ int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned s
 
 static_assert(kMaxBatch == kMaxBatchMembers, "grouped launch capacity");
 
-// One phase of several instances in one launch (128 x 128 tiles, 16 waves).
-hipError_t launch_dense_phase_bf16_group(const Bf16GroupMember *m, int n, hipStream_t s)
+struct BatchCaps {
+    int n;
+    int lslot[kMaxBatch], kmax[kMaxBatch];
+};
+
+__global__ void k_batch_advance(int *level, BatchCaps c)
+{
+    const int i = threadIdx.x;
+    if (i < c.n) {
+        const int k = level[c.lslot[i]];
+        level[c.lslot[i]] = k < c.kmax[i] ? k + 1 : k;
+    }
+}
+
+hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipStream_t s)
 {
     if (n < 1 || n > kMaxBatch)
         return hipErrorInvalidValue;
-    Bf16GroupArgs a;
-    a.n = n;
-    int tile0 = 0;
+    Bf16BatchArgs a;
+    a.level = level;
+    int maxB = 0;
     for (int i = 0; i < n; ++i) {
         const Instance &I = *m[i].I;
-        Bf16PhaseDesc &d = a.d[i];
+        Bf16BatchMember &d = a.mem[i];
         d.J = I.Jbf;
-        d.Mold = m[i].Mold;
-        d.Mnew = m[i].Mnew;
-        d.invT = m[i].invT;
+        d.Ma = m[i].Ma;
+        d.Mb = m[i].Mb;
+        d.table = m[i].table;
         d.hhalf = I.has_h ? I.hhalf : nullptr;
-        d.ldj = I.Np;
         d.ldk = I.Np;
         d.R = m[i].R;
-        d.p0 = m[i].p0;
-        d.p1 = m[i].p1;
         d.nrt = (m[i].R + 127) / 128;
-        d.nct = (m[i].p1 - m[i].p0 + 127) / 128;
         d.kpad = (I.N + HBK - 1) / HBK * HBK;
+        d.ldt = m[i].ldt;
+        d.kmax = m[i].kmax;
+        d.lslot = m[i].lslot;
         d.gamma = m[i].gamma;
-        d.tile0 = tile0;
-        d.blend = (m[i].p0 % 8) != 0;
-        tile0 += (d.nrt * d.nct + 7) / 8 * 8;  // next instance starts on a multiple of 8
+        maxB = std::max(maxB, m[i].B);
     }
-    hipLaunchKernelGGL((k_dense_phase_bf16_group<128, 128, 4, 4, 2, HBK>), dim3(tile0), dim3(1024), 0, s, a);
+    for (int ph = 0; ph < maxB; ++ph) {
+        int ns = 0, tile0 = 0;
+        for (int i = 0; i < n; ++i) {
+            if (ph >= m[i].B || m[i].pb[ph + 1] <= m[i].pb[ph])
+                continue;
+            Bf16BatchSlot &sl = a.slot[ns++];
+            sl.member = i;
+            sl.p0 = m[i].pb[ph];
+            sl.p1 = m[i].pb[ph + 1];
+            sl.nct = (sl.p1 - sl.p0 + 127) / 128;
+            sl.tile0 = tile0;
+            sl.blend = (sl.p0 % 8) != 0;
+            tile0 += (a.mem[i].nrt * sl.nct + 7) / 8 * 8;  // next member starts on a multiple of 8
+        }
+        a.nslot = ns;
+        if (ns == 0)
+            continue;
+        hipLaunchKernelGGL((k_dense_phase_bf16_batch<128, 128, 4, 4, 2, HBK>), dim3(tile0), dim3(1024), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    BatchCaps c;
+    c.n = n;
+    for (int i = 0; i < n; ++i) {
+        c.lslot[i] = m[i].lslot;
+        c.kmax[i] = m[i].kmax;
+    }
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, level, c);
     return hipGetLastError();
 }
 

@@ -151,17 +151,20 @@ void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsi
                              hipStream_t s);
 int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R, int p0,
                        int p1, const float *invT, float gamma, hipStream_t s);
-// one member of a grouped phase launch (the batched solver)
-struct Bf16GroupMember {
+// one member of the batched solver's launches
+struct BatchMemberDesc {
     const Instance *I;
-    const unsigned short *Mold;
-    unsigned short *Mnew;
-    const float *invT;  // this member's level row of 1/T
-    int R, p0, p1;
+    unsigned short *Ma, *Mb;  // state buffers (level k reads Ma if k is even)
+    const float *table;       // 1/T: row k at table + k * ldt
+    const int *pb;            // B + 1 phase bounds
+    int R, ldt, kmax, B, lslot;  // lslot: the member's level counter
     float gamma;
 };
 constexpr int kMaxBatchMembers = 16;
-hipError_t launch_dense_phase_bf16_group(const Bf16GroupMember *m, int n, hipStream_t s);
+// One sweep of the members: one launch per phase index over the tiles of
+// every member that has that phase, then the level advance (level[lslot] += 1
+// below kmax).  Kernel launches only, so it can be captured in a graph.
+hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipStream_t s);
 void launch_bf16_round(const unsigned short *MT, int ldk, int N, int R, int Ke, int8_t *spad, int8_t *spins,
                        float *m_final, hipStream_t s);
 

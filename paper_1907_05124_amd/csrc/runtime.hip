@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <thread>
@@ -926,8 +927,8 @@ static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, ui
 struct BatchMember {
     Instance *I = nullptr;
     DenseRun d;
-    int k = 0;  // next level
-    void *cur = nullptr, *nxt = nullptr;
+    int k = 0;      // next level (mirrors the device counter)
+    int lslot = -1;  // index of the member's device level counter
     int64_t tag = 0;
     int8_t *best = nullptr;
     mars_result *res_pinned = nullptr;
@@ -941,10 +942,27 @@ struct Batch {
     hipStream_t s = nullptr;
     std::mutex mu;
     std::vector<BatchMember> members;
+    int *level = nullptr;  // [kMaxBatchMembers] device level counters
+    uint32_t used = 0;     // level counters in use (bit mask)
+    // graph of a whole step (sweeps x sweep), valid while the membership
+    // and the sweep count are unchanged
+    bool graphs = true;
+    hipGraphExec_t exec = nullptr;
+    int exec_sweeps = 0;
 };
 
-static void release_member(BatchMember &m)
+static void drop_graph(Batch &b)
 {
+    if (b.exec)
+        (void)hipGraphExecDestroy(b.exec);
+    b.exec = nullptr;
+    b.exec_sweeps = 0;
+}
+
+static void release_member(Batch &b, BatchMember &m)
+{
+    if (m.lslot >= 0)
+        b.used &= ~(1u << m.lslot);
     std::lock_guard<std::mutex> lk(m.I->mu);
     m.I->in_batch = false;
 }
@@ -953,8 +971,10 @@ static void release_member(BatchMember &m)
 // copies to the caller's buffers
 static mars_status finish_member(Batch &b, BatchMember &m)
 {
+    // the state after the last level is in Ma when kmax is even, else in Mb
+    const void *cur = (m.d.kmax & 1) ? m.d.Mb : m.d.Ma;
     launch_dense_runstat(m.d.R, m.d.nlev, (int64_t *)m.I->ws.runstat.p, b.s);
-    mars_status st = dense_finish(m.I, m.d, m.cur, nullptr, nullptr, m.E, m.best, m.res_dev, m.best_dev, b.s);
+    mars_status st = dense_finish(m.I, m.d, cur, nullptr, nullptr, m.E, m.best, m.res_dev, m.best_dev, b.s);
     if (st == MARS_OK && m.res_pinned) {
         hipError_t e = hipMemcpyAsync(m.res_pinned, m.res_dev, sizeof(mars_result), hipMemcpyDeviceToHost, b.s);
         if (e != hipSuccess)
@@ -962,7 +982,7 @@ static mars_status finish_member(Batch &b, BatchMember &m)
     }
     if (st == MARS_OK)
         st = order_end(m.I, b.s);
-    release_member(m);
+    release_member(b, m);
     return st;
 }
 
@@ -993,12 +1013,13 @@ static mars_status batch_add(Batch &b, Instance *I, int R, const mars_schedule *
     m.res_pinned = res_pinned;
     Workspace &w = I->ws;
     auto fail = [&](mars_status e) {
-        release_member(m);
+        release_member(b, m);
         return e;
     };
     if ((st = order_begin(I, b.s)) != MARS_OK)
         return fail(st);
-    if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK || (st = ensure(w.energies, sizeof(double) * R)) != MARS_OK ||
+    if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK ||
+        (st = ensure(w.energies, sizeof(double) * R)) != MARS_OK ||
         (st = ensure(w.partial, dense_energy_partial_bytes(*I, R))) != MARS_OK)
         return fail(st);
     m.E = (double *)w.energies.p;
@@ -1006,68 +1027,112 @@ static mars_status batch_add(Batch &b, Instance *I, int R, const mars_schedule *
     m.best_dev = (int32_t *)((char *)w.result.p + sizeof(mars_result) + 16);
     if ((st = dense_setup(I, R, *sc, seed, nullptr, nullptr, m.d, b.s)) != MARS_OK)
         return fail(st);
-    m.cur = m.d.Ma;
-    m.nxt = m.d.Mb;
+    for (int q = 0; q < kMaxBatchMembers; ++q)
+        if (!(b.used & (1u << q))) {
+            m.lslot = q;
+            break;
+        }
+    b.used |= 1u << m.lslot;
+    launch_fill_u32(reinterpret_cast<uint32_t *>(b.level + m.lslot), 0u, 1, b.s);
+    MARS_HIP(hipGetLastError());
     b.members.push_back(m);
+    drop_graph(b);
     return MARS_OK;
+}
+
+static void describe(const Batch &b, BatchMemberDesc *dm)
+{
+    for (size_t i = 0; i < b.members.size(); ++i) {
+        const BatchMember &m = b.members[i];
+        dm[i].I = m.I;
+        dm[i].Ma = (unsigned short *)m.d.Ma;
+        dm[i].Mb = (unsigned short *)m.d.Mb;
+        dm[i].table = m.d.table;
+        dm[i].pb = m.d.pb.data();
+        dm[i].R = m.d.R;
+        dm[i].ldt = m.d.ldt;
+        dm[i].kmax = m.d.kmax;
+        dm[i].B = m.d.B;
+        dm[i].lslot = m.lslot;
+        dm[i].gamma = m.d.gamma;
+    }
+}
+
+// Members past their last level leave, as long as the tag array has room
+// (the others leave at a later call; their launches exit at once meanwhile).
+static mars_status retire(Batch &b, int64_t *tags, int cap, int *n_fin)
+{
+    mars_status st = MARS_OK;
+    for (size_t i = 0; i < b.members.size() && *n_fin < cap;) {
+        BatchMember &m = b.members[i];
+        if (m.k < m.d.kmax) {
+            ++i;
+            continue;
+        }
+        mars_status e = finish_member(b, m);
+        if (e != MARS_OK && st == MARS_OK)
+            st = e;
+        tags[(*n_fin)++] = m.tag;
+        b.members.erase(b.members.begin() + (long)i);
+        drop_graph(b);
+    }
+    return st;
 }
 
 static mars_status batch_step(Batch &b, int sweeps, int64_t *tags, int cap, int *n_fin)
 {
     *n_fin = 0;
-    mars_status st = MARS_OK;
-    // members past their last level leave (as long as the tag array has room;
-    // the others leave at a later call and are not swept meanwhile)
-    auto retire = [&]() {
-        for (size_t i = 0; i < b.members.size() && *n_fin < cap;) {
-            BatchMember &m = b.members[i];
-            if (m.k < m.d.kmax) {
-                ++i;
-                continue;
+    mars_status st = retire(b, tags, cap, n_fin);
+    bool active = false;
+    for (const BatchMember &m : b.members)
+        active |= m.k < m.d.kmax;
+    if (st != MARS_OK || sweeps == 0 || !active)
+        return st;
+    BatchMemberDesc dm[kMaxBatchMembers];
+    describe(b, dm);
+    const int n = (int)b.members.size();
+    if (b.graphs && b.s) {
+        // the whole step as one graph launch, captured once per membership
+        if (!b.exec || b.exec_sweeps != sweeps) {
+            drop_graph(b);
+            hipGraph_t g = nullptr;
+            MARS_HIP(hipStreamBeginCapture(b.s, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int sw = 0; sw < sweeps && e == hipSuccess; ++sw)
+                e = launch_batch_sweep(dm, n, b.level, b.s);
+            const hipError_t e2 = hipStreamEndCapture(b.s, &g);
+            if (e == hipSuccess)
+                e = e2;
+            if (e == hipSuccess)
+                e = hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0);
+            if (g)
+                (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                b.exec = nullptr;
+                return hip_error(e, "capturing the batch step");
             }
-            mars_status e = finish_member(b, m);
-            if (e != MARS_OK && st == MARS_OK)
-                st = e;
-            tags[(*n_fin)++] = m.tag;
-            b.members.erase(b.members.begin() + (long)i);
+            b.exec_sweeps = sweeps;
         }
-    };
-    retire();
-    Bf16GroupMember g[kMaxBatchMembers];
-    for (int sw = 0; sw < sweeps && st == MARS_OK; ++sw) {
-        int maxB = 0;
-        for (const BatchMember &m : b.members)
-            if (m.k < m.d.kmax)
-                maxB = std::max(maxB, m.d.B);
-        if (maxB == 0)
-            break;
-        for (int ph = 0; ph < maxB; ++ph) {
-            int n = 0;
-            for (const BatchMember &m : b.members) {
-                if (m.k >= m.d.kmax || ph >= m.d.B || m.d.pb[ph + 1] <= m.d.pb[ph])
-                    continue;
-                g[n].I = m.I;
-                g[n].Mold = (const unsigned short *)m.cur;
-                g[n].Mnew = (unsigned short *)m.nxt;
-                g[n].invT = m.d.table + (size_t)m.k * m.d.ldt;
-                g[n].R = m.d.R;
-                g[n].p0 = m.d.pb[ph];
-                g[n].p1 = m.d.pb[ph + 1];
-                g[n].gamma = m.d.gamma;
-                ++n;
-            }
-            if (n > 0) {
-                hipError_t e = launch_dense_phase_bf16_group(g, n, b.s);
-                if (e != hipSuccess)
-                    return hip_error(e, "grouped phase launch");
-            }
-        }
+        MARS_HIP(hipGraphLaunch(b.exec, b.s));
         for (BatchMember &m : b.members)
-            if (m.k < m.d.kmax) {
-                std::swap(m.cur, m.nxt);
-                ++m.k;
-            }
-        retire();
+            m.k = std::min(m.k + sweeps, m.d.kmax);
+        return retire(b, tags, cap, n_fin);
+    }
+    // eager: one sweep at a time, members leave as soon as they finish
+    for (int sw = 0; sw < sweeps && st == MARS_OK && !b.members.empty(); ++sw) {
+        describe(b, dm);
+        const int nm = (int)b.members.size();
+        bool any = false;
+        for (const BatchMember &m : b.members)
+            any |= m.k < m.d.kmax;
+        if (!any)
+            break;
+        hipError_t e = launch_batch_sweep(dm, nm, b.level, b.s);
+        if (e != hipSuccess)
+            return hip_error(e, "batch sweep launch");
+        for (BatchMember &m : b.members)
+            m.k = std::min(m.k + 1, m.d.kmax);
+        st = retire(b, tags, cap, n_fin);
     }
     return st;
 }
@@ -1306,6 +1371,13 @@ mars_status mars_batch_create(void *stream, mars_batch **out)
         return hip_error(e, "hipGetDevice");
     }
     b->s = reinterpret_cast<hipStream_t>(stream);
+    e = hipMalloc(&b->level, sizeof(int) * kMaxBatchMembers);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_error(e, "hipMalloc batch level counters");
+    }
+    if (const char *f = std::getenv("MARS_BATCH_GRAPH"))
+        b->graphs = std::atoi(f) != 0;
     *out = reinterpret_cast<mars_batch *>(b);
     return MARS_OK;
 }
@@ -1347,9 +1419,11 @@ void mars_batch_destroy(mars_batch *batch)
         (void)hipStreamSynchronize(b->s);
         for (BatchMember &m : b->members) {
             (void)order_end(m.I, b->s);
-            release_member(m);
+            release_member(*b, m);
         }
         b->members.clear();
+        drop_graph(*b);
+        (void)hipFree(b->level);
     }
     delete b;
 }

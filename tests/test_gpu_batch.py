@@ -44,7 +44,11 @@ def _pinned(M):
     return torch.zeros(256, dtype=torch.uint8, pin_memory=True)
 
 
-def test_batch_equals_alone():
+@pytest.mark.parametrize("graph", ["1", "0"])
+def test_batch_equals_alone(graph, monkeypatch):
+    """Steps run as one captured graph per membership (replayed while the
+    membership holds) or sweep by sweep; both equal the solves alone."""
+    monkeypatch.setenv("MARS_BATCH_GRAPH", graph)
     M = _mars()
     import torch
 
@@ -53,7 +57,7 @@ def test_batch_equals_alone():
     cases[-1] = (cases[-1][0], cases[-1][1], cases[-1][2].replace(update="jacobi"), cases[-1][3])
     cases.append(_case(90, 40, 2, 8, 0.0, 8))
     cases[-1] = (cases[-1][0], cases[-1][1], cases[-1][2].replace(level_count=0), cases[-1][3])
-    announce("batch vs alone", len(cases))
+    announce("batch vs alone", len(cases), "graph", graph)
     handles = [M.Instance.from_inputs(c[0]) for c in cases]
     alone = [h.solve_ex(R, sch, seed, want_best=True) for h, (_, R, sch, seed) in zip(handles, cases)]
     torch.cuda.synchronize()
@@ -85,7 +89,9 @@ def test_batch_equals_alone():
         h.close()
 
 
-def test_batch_full_and_refusals():
+@pytest.mark.parametrize("graph", ["1", "0"])
+def test_batch_full_and_refusals(graph, monkeypatch):
+    monkeypatch.setenv("MARS_BATCH_GRAPH", graph)
     M = _mars()
     import torch
 
@@ -124,12 +130,20 @@ def test_batch_full_and_refusals():
         while len(batch):
             done, _ = batch.step(2, cap=16)
             total += done
+        # a second round on the same batch: members join again, the step
+        # graph is captured anew and replayed
+        for t in range(4):
+            batch.add(handles[t], 64, sch, 100 + t, 100 + t, bufs[t])
+        while len(batch):
+            done, _ = batch.step(3, cap=16)
+            total += done
         batch.close()
     stream.synchronize()
-    assert sorted(total) == list(range(M.Batch.MAX_MEMBERS))
+    assert sorted(total) == list(range(M.Batch.MAX_MEMBERS)) + [100, 101, 102, 103]
     # released: the instances solve alone again, with the batch's results
-    r_alone = handles[0].solve_ex(64, sch, 0)["result"]
-    assert r_alone == M.Instance.read_result(bufs[0])
+    for t in range(4):
+        r_alone = handles[t].solve_ex(64, sch, 100 + t)["result"]
+        assert r_alone == M.Instance.read_result(bufs[t])
     for h in handles:
         h.close()
 
