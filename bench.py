@@ -99,6 +99,7 @@ def cpu_baseline(w, seed, budget_s=12.0):
     sch = w.schedule.replace(precision="fp64") if w.schedule.precision != "fp64" else w.schedule
     n = cores
     total_runs, total_t, total_upd = 0, 0.0, 0
+    spins, energies = [], []
     while True:
         t0 = time.perf_counter()
         r = O.solve(w.instance, w.runs, sch, seed, run_begin=total_runs, run_count=n, nthreads=cores)
@@ -106,12 +107,34 @@ def cpu_baseline(w, seed, budget_s=12.0):
         total_runs += n
         total_t += dt
         total_upd += int(r["sweeps"].sum()) * N
+        spins.append(r["spins"])
+        energies.append(r["energy"])
         if total_t >= budget_s or total_runs >= w.runs:
             break
         # grow the sample towards the budget
         n = max(cores, min(w.runs - total_runs, int(n * max(1.0, (budget_s - total_t) / max(dt, 1e-3)))))
-    return {"value": total_upd / total_t, "unit": "spin-updates/s", "cores": cores, "kind": "oracle",
-            "sample": "%d of %d runs at full N=%d and full schedule, %.1f s" % (total_runs, w.runs, N, total_t)}
+    import numpy as np
+
+    out = {"value": total_upd / total_t, "unit": "spin-updates/s", "cores": cores, "kind": "oracle",
+           "sample": "%d of %d runs at full N=%d and full schedule, %.1f s" % (total_runs, w.runs, N, total_t)}
+    return out, np.concatenate(spins), np.concatenate(energies)
+
+
+def vs_oracle(m, spins, energies, symmetric):
+    """The form's rounded spins and best energy against the FP64 oracle on
+    the oracle's sample of runs (the first runs, same seeds): mean fraction of
+    spins that differ (up to a global flip when h = 0, where s and -s have the
+    same energy) and the relative gap of the sample's best energies."""
+    import numpy as np
+
+    n = len(energies)
+    S = m["spins"][:n]
+    diff = np.mean(S != spins, axis=1)
+    if symmetric:
+        diff = np.minimum(diff, np.mean(S != -spins, axis=1))
+    Eo = float(np.min(energies))
+    Eg = float(np.min(m["energies"][:n]))
+    return {"runs": int(n), "spin_mismatch": float(np.mean(diff)), "best_gap": (Eg - Eo) / abs(Eo) if Eo else 0.0}
 
 
 def copy_calibration():
@@ -200,8 +223,8 @@ def main():
             sys.exit(2)
         return served(args)
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (runs would shard by index "
-              "across GPUs; see the design notes).  Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU and has no multi-GPU path (runs would shard by index across GPUs, "
+              "with one all-reduce-min of the best energies per instance).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -251,10 +274,12 @@ def main():
         ms = float(np.mean(step_ms))
         log("%s: timed %d steps: %.3f ms/step (wall %.3f s)" % (prec, args.steps, ms, wall))
         # the same solve once more with host results: update count and summary
-        once = inst.solve_ex(R, sch, args.seed, want_best=True, sync=True, stream=stream)
+        once = inst.solve_ex(R, sch, args.seed, want_best=True, want_spins=True, sync=True, stream=stream)
         res = once["result"]
         out = {"precision": prec, "ms_per_step": ms, "value": int(res["spin_updates"]) / (ms * 1e-3),
-               "step_ms": step_ms, "result": res, "roofline": None, "energies": once["energies"].cpu().numpy()}
+               "step_ms": step_ms, "result": res, "roofline": None, "energies": once["energies"].cpu().numpy(),
+               "spins": once["spins"].cpu().numpy()}
+        del once
         # solve with no levels (draws, rounding, energies, best-of-runs), timed
         # with events on the same stream: the solve minus it is the time of
         # the anneal kernels
@@ -319,8 +344,13 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        cpu = cpu_baseline(w, args.seed)
+        cpu, o_spins, o_energies = cpu_baseline(w, args.seed)
         log("cpu baseline", cpu)
+        h = getattr(w.instance, "h", None)
+        symmetric = h is None or not np.any(h)
+        for p in forms:
+            forms_out[p]["vs_oracle"] = vs_oracle(measured[p], o_spins, o_energies, symmetric)
+        log("vs oracle", {p: forms_out[p]["vs_oracle"] for p in forms})
 
     dtype = {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "fp16": "f16-store/f32"}[w.schedule.precision]
     line = {

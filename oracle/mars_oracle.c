@@ -7,8 +7,8 @@
  * suite, the smoke check and the benchmark's CPU-baseline leg may load it.
  * It shares no code with the GPU library.
  *
- * Conventions (readings of the paper; each one is listed with its reason in
- * the design notes of the repository):
+ * Conventions (readings of the paper where it is silent, ambiguous or
+ * garbled; each states the passage it follows):
  *
  *  - Energy (section "Ising Spin Glass Model", eq. (2), ordered-pair double
  *    sum over j != i), written with the minimisation sign used by the library
