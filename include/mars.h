@@ -195,6 +195,21 @@ mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_sched
  * the call returns after enqueueing.  Errors: MARS_E_ARG, MARS_E_DEVICE. */
 mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, double *energies, void *stream);
 
+/* Extreme eigenvalues of the couplings J (h is not involved), estimated by
+ * `steps` Lanczos steps (capped at N) from a start vector drawn with `seed`,
+ * in fp64 on the device.  They set the temperature scale of an anneal: the
+ * update of Algorithm 1 linearised at m = 0 is m <- J m / T (h = 0), so a
+ * random start decays to 0 at every T above lambda_max, and the synchronous
+ * update turns unstable below |lambda_min| (section "Mean-field Annealing
+ * from Random State"; the paper picks its temperature range by preliminary
+ * runs, section "Parameter settings").  The estimates lie inside the true
+ * range and approach it as steps grow (100 steps: within 1e-3 relative on
+ * the SK, lattice and random-graph workloads).  lambda_min, lambda_max: HOST
+ * doubles.  stream as in mars_solve_ex; the call waits for its own work.
+ * Errors: MARS_E_ARG, MARS_E_OOM, MARS_E_DEVICE. */
+mars_status mars_spectrum(mars_instance *inst, int32_t steps, uint64_t seed, double *lambda_min, double *lambda_max,
+                          void *stream);
+
 /* Batched BF16 solver for a served stream of dense instances (the BF16 form
  * of the dense field product, Algorithm 1's update, eq. (2) energies): the
  * members of a batch advance together on one stream and every update phase

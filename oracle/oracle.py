@@ -269,3 +269,36 @@ def best(energies):
     hits = C.c_int64(0)
     idx = lib().orc_best(e.ctypes.data, e.shape[0], C.byref(hits))
     return int(idx), int(hits.value)
+
+
+def coupling_matrix(inst) -> np.ndarray:
+    """J as a dense float64 matrix, written out from each container's
+    definition: dense J as given; CSR entry (i, col[k]) = val[k]; lattice bond
+    bond[a, i] couples site i (x0 fastest) with its neighbour one step along
+    axis a in the positive direction, wrapping around (test infrastructure)."""
+    if hasattr(inst, "J"):
+        return np.asarray(inst.J, dtype=np.float64).copy()
+    N = int(inst.N)
+    M = np.zeros((N, N), dtype=np.float64)
+    if hasattr(inst, "rowptr"):
+        for i in range(N):
+            for k in range(int(inst.rowptr[i]), int(inst.rowptr[i + 1])):
+                M[i, int(inst.col[k])] += float(inst.val[k])
+        return M
+    L = tuple(int(x) for x in inst.L)
+    strides = [1]
+    for a in range(len(L) - 1):
+        strides.append(strides[-1] * L[a])
+    for i in range(N):
+        for a in range(len(L)):
+            xa = (i // strides[a]) % L[a]
+            j = i + (((xa + 1) % L[a]) - xa) * strides[a]
+            M[i, j] += float(inst.bond[a, i])
+            M[j, i] += float(inst.bond[a, i])
+    return M
+
+
+def spectrum(inst):
+    """(lambda_min, lambda_max) of J, from the symmetric eigensolver."""
+    w = np.linalg.eigvalsh(coupling_matrix(inst))
+    return float(w[0]), float(w[-1])

@@ -39,6 +39,7 @@ struct Workspace {
     DevBuf result;          // device mars_result + best index
     DevBuf runstate;        // paper mode per-run level state
     DevBuf flag;            // small counters
+    DevBuf spec;            // Lanczos vectors and coefficients
 };
 
 struct Instance {
@@ -151,6 +152,10 @@ void launch_dense_phase_bf16(const Instance &I, const unsigned short *Mold, unsi
                              hipStream_t s);
 int bf16_phase_variant(const Instance &I, const unsigned short *Mold, unsigned short *Mnew, int ldk, int R, int p0,
                        int p1, const float *invT, float gamma, hipStream_t s);
+// Lanczos iteration on J (steps <= N): vecs holds 4 N doubles; the
+// recurrence coefficients alpha[steps], beta[steps] stay on the device.
+hipError_t launch_spectrum_lanczos(const Instance &I, int steps, uint64_t seed, double *vecs, double *alpha,
+                                   double *beta, hipStream_t s);
 // one member of the batched solver's launches
 struct BatchMemberDesc {
     const Instance *I;

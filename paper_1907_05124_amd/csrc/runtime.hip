@@ -1357,6 +1357,92 @@ mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, dou
     return order_end(I, s);
 }
 
+// Smallest and largest eigenvalues of the symmetric tridiagonal matrix with
+// diagonal a[0..m) and off-diagonal b[0..m-1), by bisection on Sturm counts
+// (count(x) = number of eigenvalues below x, from the signs of the pivots of
+// T - x I).
+static void tridiag_extremes(const std::vector<double> &a, const std::vector<double> &b, int m, double *lo_out,
+                             double *hi_out)
+{
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    const double pad = 1e-12 * std::max(1.0, std::max(std::fabs(lo), std::fabs(hi)));
+    lo -= pad;
+    hi += pad;
+    auto count = [&](double x) {
+        int c = 0;
+        double d = 1.0;
+        for (int i = 0; i < m; ++i) {
+            d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+            if (d == 0.0)
+                d = -1e-300;
+            c += d < 0.0;
+        }
+        return c;
+    };
+    auto bisect = [&](int k) {  // the (k+1)-th smallest eigenvalue
+        double l = lo, h = hi;
+        for (int it = 0; it < 200 && h - l > 1e-15 * std::max(std::fabs(l), std::fabs(h)); ++it) {
+            const double mid = 0.5 * (l + h);
+            if (count(mid) > k)
+                h = mid;
+            else
+                l = mid;
+        }
+        return 0.5 * (l + h);
+    };
+    *lo_out = bisect(0);
+    *hi_out = bisect(m - 1);
+}
+
+mars_status mars_spectrum(mars_instance *inst, int32_t steps, uint64_t seed, double *lambda_min, double *lambda_max,
+                          void *stream)
+{
+    if (!inst || !lambda_min || !lambda_max || steps < 1)
+        return set_error(MARS_E_ARG, "need instance, outputs and steps >= 1");
+    Instance *I = reinterpret_cast<Instance *>(inst);
+    std::lock_guard<std::mutex> lk(I->mu);
+    if (I->in_batch)
+        return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
+    MARS_HIP(hipSetDevice(I->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int N = I->N;
+    const int k = std::min(steps, N);
+    mars_status st = order_begin(I, s);
+    if (st != MARS_OK)
+        return st;
+    if ((st = ensure(I->ws.spec, sizeof(double) * (4 * (size_t)N + 2 * (size_t)k))) != MARS_OK)
+        return st;
+    double *vecs = (double *)I->ws.spec.p;
+    double *alpha = vecs + 4 * (size_t)N, *beta = alpha + k;
+    MARS_HIP(launch_spectrum_lanczos(*I, k, seed, vecs, alpha, beta, s));
+    std::vector<double> a((size_t)k), b((size_t)k);
+    MARS_HIP(hipMemcpyAsync(a.data(), alpha, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    MARS_HIP(hipMemcpyAsync(b.data(), beta, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    if ((st = order_end(I, s)) != MARS_OK)
+        return st;
+    MARS_HIP(hipStreamSynchronize(s));
+    // the Krylov space closes at the first vanishing beta (an invariant subspace)
+    double scale = 0.0;
+    for (int j = 0; j < k; ++j)
+        scale = std::max(scale, std::fabs(a[j]) + std::fabs(b[j]));
+    int m = k;
+    for (int j = 0; j + 1 < k; ++j)
+        if (!(b[j] > 1e-13 * scale)) {
+            m = j + 1;
+            break;
+        }
+    for (int j = 0; j < m; ++j)
+        if (!std::isfinite(a[j]) || !std::isfinite(b[j]))
+            return set_error(MARS_E_DEVICE, "Lanczos coefficients are not finite");
+    tridiag_extremes(a, b, m, lambda_min, lambda_max);
+    return MARS_OK;
+}
+
 mars_status mars_batch_create(void *stream, mars_batch **out)
 {
     if (!out)

@@ -51,7 +51,7 @@ class Result(C.Structure):
 
 
 EXPORTS = ["mars_create", "mars_create_csr", "mars_create_lattice", "mars_destroy", "mars_describe", "mars_solve",
-           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_batch_create", "mars_batch_add",
+           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_spectrum", "mars_batch_create", "mars_batch_add",
            "mars_batch_step", "mars_batch_destroy", "mars_status_str", "mars_last_error"]
 
 _lib = None
@@ -79,6 +79,7 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(Result), vp]
         L.mars_solve_async.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mars_energy.argtypes = [vp, vp, i32, vp, vp]
+        L.mars_spectrum.argtypes = [vp, i32, u64, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
         L.mars_batch_create.argtypes = [vp, C.POINTER(vp)]
         L.mars_batch_add.argtypes = [vp, vp, i32, C.POINTER(Schedule), u64, C.c_int64, vp, vp]
         L.mars_batch_step.argtypes = [vp, i32, vp, i32, C.POINTER(i32), C.POINTER(i32)]
@@ -89,7 +90,7 @@ def load(path: str = LIB_PATH):
         L.mars_last_error.argtypes = []
         L.mars_last_error.restype = C.c_char_p
         for f in ("mars_create", "mars_create_csr", "mars_create_lattice", "mars_describe", "mars_solve",
-                  "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_batch_create", "mars_batch_add",
+                  "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_spectrum", "mars_batch_create", "mars_batch_add",
                   "mars_batch_step"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -268,6 +269,15 @@ class Instance:
         """Decode a pinned result buffer filled by solve_async (after the stream passed it)."""
         raw = bytes(result_buf.cpu().numpy()[: C.sizeof(Result)])
         return Result.from_buffer_copy(raw).as_dict()
+
+    def spectrum(self, steps: int = 100, seed: int = 1):
+        """(lambda_min, lambda_max) of J by `steps` Lanczos steps on the device."""
+        import torch
+
+        lo, hi = C.c_double(), C.c_double()
+        _check(load().mars_spectrum(self._h, int(steps), seed & (2**64 - 1), C.byref(lo), C.byref(hi),
+                                    C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return lo.value, hi.value
 
     def energy(self, spins):
         """Exact energies of device spins [R, N] int8 -> float64 [R] (current stream)."""
