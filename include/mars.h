@@ -210,6 +210,20 @@ mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, dou
 mars_status mars_spectrum(mars_instance *inst, int32_t steps, uint64_t seed, double *lambda_min, double *lambda_max,
                           void *stream);
 
+/* Temperature range from the spectrum: runs mars_spectrum(steps, seed) and
+ * sets sched->T_lo = 0.5 L, T_hi = 1.5 L and T_end = 0.005 L, with
+ * L = lambda_max (the spectral radius if J has no positive eigenvalue); the
+ * other fields are left as they are.  This stands in for the preliminary
+ * runs with which the paper chooses its temperature bounds (section
+ * "Parameter settings"; the paper stresses that the bounds are what matters).
+ * The factors come from a sweep over SK, random-graph and 2D/3D lattice
+ * instances, where this range reached best energies 1-1.5 % lower than a
+ * range scaled by the field deviation sigma_Phi = sqrt(mean_i sum_j J_ij^2)
+ * on lattices and degree-4 graphs, and equal ones on SK and dense graphs.
+ * Errors: those of mars_spectrum; MARS_E_ARG if sched is NULL or J = 0. */
+mars_status mars_auto_temperatures(mars_instance *inst, int32_t steps, uint64_t seed, mars_schedule *sched,
+                                   void *stream);
+
 /* Batched BF16 solver for a served stream of dense instances (the BF16 form
  * of the dense field product, Algorithm 1's update, eq. (2) energies): the
  * members of a batch advance together on one stream and every update phase

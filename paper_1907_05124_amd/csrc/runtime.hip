@@ -1443,6 +1443,26 @@ mars_status mars_spectrum(mars_instance *inst, int32_t steps, uint64_t seed, dou
     return MARS_OK;
 }
 
+mars_status mars_auto_temperatures(mars_instance *inst, int32_t steps, uint64_t seed, mars_schedule *sched,
+                                   void *stream)
+{
+    if (!sched)
+        return set_error(MARS_E_ARG, "schedule is NULL");
+    double lo = 0.0, hi = 0.0;
+    mars_status st = mars_spectrum(inst, steps, seed, &lo, &hi, stream);
+    if (st != MARS_OK)
+        return st;
+    // the scale: lambda_max, where the random start stops decaying; if J has
+    // no positive eigenvalue, the spectral radius
+    const double scale = hi > 0.0 ? hi : std::max(std::fabs(lo), std::fabs(hi));
+    if (!(scale > 0.0) || !std::isfinite(scale))
+        return set_error(MARS_E_ARG, "J has no nonzero eigenvalue: no temperature scale");
+    sched->T_lo = 0.5 * scale;
+    sched->T_hi = 1.5 * scale;
+    sched->T_end = 0.005 * scale;
+    return MARS_OK;
+}
+
 mars_status mars_batch_create(void *stream, mars_batch **out)
 {
     if (!out)

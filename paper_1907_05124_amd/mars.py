@@ -51,8 +51,9 @@ class Result(C.Structure):
 
 
 EXPORTS = ["mars_create", "mars_create_csr", "mars_create_lattice", "mars_destroy", "mars_describe", "mars_solve",
-           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_spectrum", "mars_batch_create", "mars_batch_add",
-           "mars_batch_step", "mars_batch_destroy", "mars_status_str", "mars_last_error"]
+           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_spectrum", "mars_auto_temperatures",
+           "mars_batch_create", "mars_batch_add", "mars_batch_step", "mars_batch_destroy", "mars_status_str",
+           "mars_last_error"]
 
 _lib = None
 _lock = threading.Lock()
@@ -80,6 +81,7 @@ def load(path: str = LIB_PATH):
         L.mars_solve_async.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mars_energy.argtypes = [vp, vp, i32, vp, vp]
         L.mars_spectrum.argtypes = [vp, i32, u64, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
+        L.mars_auto_temperatures.argtypes = [vp, i32, u64, C.POINTER(Schedule), vp]
         L.mars_batch_create.argtypes = [vp, C.POINTER(vp)]
         L.mars_batch_add.argtypes = [vp, vp, i32, C.POINTER(Schedule), u64, C.c_int64, vp, vp]
         L.mars_batch_step.argtypes = [vp, i32, vp, i32, C.POINTER(i32), C.POINTER(i32)]
@@ -90,8 +92,8 @@ def load(path: str = LIB_PATH):
         L.mars_last_error.argtypes = []
         L.mars_last_error.restype = C.c_char_p
         for f in ("mars_create", "mars_create_csr", "mars_create_lattice", "mars_describe", "mars_solve",
-                  "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_spectrum", "mars_batch_create", "mars_batch_add",
-                  "mars_batch_step"):
+                  "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_spectrum", "mars_auto_temperatures",
+                  "mars_batch_create", "mars_batch_add", "mars_batch_step"):
             getattr(L, f).restype = C.c_int
         _lib = L
         return L
@@ -278,6 +280,16 @@ class Instance:
         _check(load().mars_spectrum(self._h, int(steps), seed & (2**64 - 1), C.byref(lo), C.byref(hi),
                                     C.c_void_p(torch.cuda.current_stream().cuda_stream)))
         return lo.value, hi.value
+
+    def auto_temperatures(self, schedule, steps: int = 100, seed: int = 1):
+        """`schedule` (an inputs.Schedule) with T_lo, T_hi, T_end set from the
+        spectrum of J by the library (mars_auto_temperatures)."""
+        import torch
+
+        s = make_schedule(schedule)
+        _check(load().mars_auto_temperatures(self._h, int(steps), seed & (2**64 - 1), C.byref(s),
+                                             C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return schedule.replace(T_lo=s.T_lo, T_hi=s.T_hi, T_end=s.T_end)
 
     def energy(self, spins):
         """Exact energies of device spins [R, N] int8 -> float64 [R] (current stream)."""

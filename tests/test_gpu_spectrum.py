@@ -57,3 +57,39 @@ def test_spectrum_arguments():
         lo, hi = g.spectrum(1000)  # capped at N
         elo, ehi = O.spectrum(I.sk_instance(20, 1))
         assert abs(lo - elo) < 1e-9 and abs(hi - ehi) < 1e-9
+
+
+def test_auto_temperatures_fields():
+    """T_lo, T_hi, T_end are 0.5, 1.5 and 0.005 times lambda_max (same
+    Lanczos run as mars_spectrum); the other schedule fields are untouched."""
+    require_gpu()
+    from paper_1907_05124_amd import mars as M
+
+    inst = I.er_instance(500, 8, avg_degree=4.0, weights="pm1")
+    base = I.Schedule(T_lo=9.0, T_hi=10.0, T_end=1.0, steps=123, phases=3, damping=0.75, precision="fp16")
+    with M.Instance.from_inputs(inst) as g:
+        _, hi = g.spectrum(80, seed=5)
+        sch = g.auto_temperatures(base, steps=80, seed=5)
+    assert (sch.T_lo, sch.T_hi, sch.T_end) == (0.5 * hi, 1.5 * hi, 0.005 * hi)
+    assert sch.replace(T_lo=9.0, T_hi=10.0, T_end=1.0) == base
+
+
+@pytest.mark.parametrize("case", ["ea2d_32", "er5000"])
+def test_auto_temperatures_reach_lower_energy(case):
+    """On a 2D +-J lattice and a degree-4 random graph the spectrum-scaled
+    range reaches a lower best energy (same runs and seeds) than the range
+    scaled by the field deviation, T0 ~ sigma U[0.25, 1.5] to 0.01 sigma."""
+    require_gpu()
+    from paper_1907_05124_amd import mars as M
+
+    inst = {"ea2d_32": lambda: I.lattice_instance((32, 32), 14),
+            "er5000": lambda: I.er_instance(5000, 16, avg_degree=4.0, weights="pm1")}[case]()
+    s = I.field_scale(inst)
+    base = I.Schedule(T_lo=0.25 * s, T_hi=1.5 * s, T_end=0.01 * s, steps=300, phases=2, precision="fp32")
+    announce("auto temperatures", case)
+    with M.Instance.from_inputs(inst) as g:
+        auto = g.auto_temperatures(base, steps=150, seed=3)
+        e_sigma = g.solve_ex(512, base, 9)["result"]["best_energy"]
+        e_auto = g.solve_ex(512, auto, 9)["result"]["best_energy"]
+    print("best energy per spin: sigma range %.5f, spectrum range %.5f" % (e_sigma / inst.N, e_auto / inst.N))
+    assert e_auto < e_sigma
