@@ -34,8 +34,8 @@ TRAFFIC_RECORD = {
     "fp32": {"source": "paper_1907_05124_amd/csrc/dense_phase.h", "sha256_prefix": "f9fb3b74ef6c09ae",
              "workload": "sk2000", "fetch_kib": 54875.6, "write_kib": 16000.0,
              "fetch_scale": 2.0, "write_scale": 1.0, "summary": "profiles/k_dense_phase_f32_sk2000.md"},
-    "bf16": {"source": "paper_1907_05124_amd/csrc/dense_phase_bf16.h", "sha256_prefix": "422a087acbe0751d",
-             "workload": "sk2000", "fetch_kib": 26425.8, "write_kib": 8256.0,
+    "bf16": {"source": "paper_1907_05124_amd/csrc/dense_phase_bf16.h", "sha256_prefix": "237f59c1c1e9c87f",
+             "workload": "sk2000", "fetch_kib": 26428.9, "write_kib": 8256.0,
              "fetch_scale": 2.0, "write_scale": 1.0, "summary": "profiles/k_dense_phase_bf16_sk2000.md"},
 }
 

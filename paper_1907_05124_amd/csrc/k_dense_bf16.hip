@@ -8,7 +8,7 @@
 #include <tuple>
 
 #include "common_device.h"
-#include "dense_phase_bf16.h"
+#include "dense_batch_bf16.h"
 #include "mars_internal.h"
 
 namespace mars {
