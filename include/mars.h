@@ -62,7 +62,7 @@ typedef enum {
 } mars_status;
 
 enum { MARS_GEOMETRIC = 0, MARS_LINEAR = 1 };
-enum { MARS_PHASED = 0, MARS_JACOBI = 1 };
+enum { MARS_PHASED = 0, MARS_JACOBI = 1, MARS_SEQUENTIAL = 2 };
 enum { MARS_FP32 = 0, MARS_FP64 = 1, MARS_BF16 = 2, MARS_FP16 = 3 };
 
 /* Annealing schedule (Algorithm 1; parameters of section "Parameter settings").
@@ -76,7 +76,12 @@ enum { MARS_FP32 = 0, MARS_FP64 = 1, MARS_BF16 = 2, MARS_FP16 = 3 };
  *   max_sweeps  sweeps allowed per level (>= 1); a level also ends when the
  *               largest change of a sweep is below d_min (the paper: 1e-4).
  *               max_sweeps = 1 gives exactly one sweep per level.
- *   update      MARS_PHASED or MARS_JACOBI.
+ *   update      MARS_PHASED, MARS_JACOBI, or MARS_SEQUENTIAL (dense MARS_FP32
+ *               only: every spin its own phase, in index order -- the
+ *               per-spin assignment of the paper's GPU description; the same
+ *               dynamics as MARS_PHASED with phases = N, computed as blocks of
+ *               64 spins whose fields come from one product and are corrected
+ *               spin by spin inside the block).
  *   phases      dense row blocks per sweep (>= 1; ignored for lattices/CSR).
  *   damping     g in (0, 1]; 1 is the paper's update.
  *   precision   MARS_FP32 (dense, lattice, CSR), MARS_FP64 (lattice, CSR),

@@ -165,8 +165,15 @@ def _sched(sc) -> _Sched:
     s.kind = GEOMETRIC if sc.kind == "geometric" else LINEAR
     s.T_lo, s.T_hi, s.T_end, s.c_step = float(sc.T_lo), float(sc.T_hi), float(sc.T_end), float(sc.c_step)
     s.steps, s.max_sweeps, s.d_min = int(sc.steps), int(sc.max_sweeps), float(sc.d_min)
-    s.update = PHASED if sc.update == "phased" else JACOBI
+    if sc.update not in ("phased", "jacobi", "sequential"):
+        raise ValueError("unknown update %r" % (sc.update,))
+    s.update = JACOBI if sc.update == "jacobi" else PHASED
     s.phases, s.damping = int(sc.phases), float(sc.damping)
+    if sc.update == "sequential":
+        # every spin its own phase in index order (Algorithm 1 with the
+        # per-spin assignment of the GPU description): phases = N, which the
+        # dense phase rule reaches by clamping
+        s.phases = 2**31 - 1
     s.first_level, s.level_count = int(sc.first_level), int(sc.level_count)
     return s
 

@@ -26,11 +26,13 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int DBM = 128, DBN = 128, DBK = 32;
 
-template <int WM, int WN, int PF>
+// RAW: instead of the update, write the field Phi = J M + h/2 of the
+// phase's rows to phi (same layout as M) for a sequential pass over them.
+template <int WM, int WN, int PF, bool RAW>
 __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
     const float *__restrict__ J, int ldj, const float *__restrict__ Mold, float *__restrict__ Mnew, int ldm, int R,
     int p0, int p1, int a0, int nrt, int nct, int kpad, const float *__restrict__ invT,
-    const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax)
+    const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax, float *__restrict__ phi)
 {
     constexpr int NT = 64 * WM * WN;
     constexpr int TM = DBM / WM, TN = DBN / WN;  // wave sub-tile
@@ -147,6 +149,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
 #undef DP_LOAD
 #undef DP_STORE
 #undef DP_MMA
+
+    if constexpr (RAW) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int col = c0 + wn * TN + b * 32 + li;
+#pragma unroll
+            for (int a = 0; a < MB; ++a)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int row = i0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * ka + (v & 3);
+                    if (col < R && row >= p0 && row < p1)
+                        phi[(size_t)row * ldm + col] = acc[a][b][v] + (hhalf ? hhalf[row] : 0.0f);
+                }
+        }
+        return;
+    }
 
     // Epilogue (Algorithm 1 with the interface's sign: m = tanh(Phi / T)).
     // 32x32 MFMA result layout: lane l holds column l%32; register v holds row

@@ -53,8 +53,78 @@ void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, i
     const int nrt = (p1 - a0 + DBM - 1) / DBM;
     const int nct = ldm / DBN;
     const int kpad = (I.N + DBK - 1) / DBK * DBK;
-    k_dense_phase_f32<DWM, DWN, DPF><<<nrt * nct, 64 * DWM * DWN, 0, s>>>(
-        I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma, dmax);
+    k_dense_phase_f32<DWM, DWN, DPF, false><<<nrt * nct, 64 * DWM * DWN, 0, s>>>(
+        I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma, dmax,
+        nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// sequential update (every spin its own phase, in index order)
+// ---------------------------------------------------------------------------
+
+// One block of SEQ_NB consecutive spins [p0, p1): phi holds their fields from
+// the state at the start of the block (J M + h/2, old values for the block's
+// own spins).  Each thread updates one run's spins in index order and adds
+// the change of each updated spin to the fields of the later ones,
+// J_ki (m_i^new - m_i^old), so every spin sees its predecessors' new values:
+// the sequential dynamics that the paper's GPU description assigns spin by
+// spin.  The block's couplings are staged in LDS (read as broadcasts).
+__global__ __launch_bounds__(64) void k_dense_seq_block(const float *__restrict__ J, int ldj,
+                                                        const float *__restrict__ phi, const float *__restrict__ Mold,
+                                                        float *__restrict__ Mnew, int ldm, int R, int p0, int p1,
+                                                        const float *__restrict__ invT, float gamma,
+                                                        uint32_t *__restrict__ dmax)
+{
+    __shared__ float Jb[SEQ_NB][SEQ_NB + 1];
+    const int n = p1 - p0;
+    for (int e = threadIdx.x; e < SEQ_NB * SEQ_NB; e += blockDim.x) {
+        const int k = e / SEQ_NB, i = e % SEQ_NB;
+        Jb[k][i] = (k < n && i < n) ? J[(size_t)(p0 + k) * ldj + p0 + i] : 0.0f;
+    }
+    __syncthreads();
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R)
+        return;
+    const float it = invT[r];  // < 0: frozen run
+    const bool damp = gamma != 1.0f;
+    float c[SEQ_NB];
+#pragma unroll
+    for (int k = 0; k < SEQ_NB; ++k)
+        c[k] = 0.0f;
+    float dl = 0.0f;
+#pragma unroll
+    for (int i = 0; i < SEQ_NB; ++i) {
+        if (i < n) {
+            const size_t at = (size_t)(p0 + i) * ldm + r;
+            const float old = Mold[at];
+            float nw = old;
+            if (it >= 0.0f) {
+                const float th = tanhf((phi[at] + c[i]) * it);
+                nw = damp ? (1.0f - gamma) * old + gamma * th : th;
+            }
+            Mnew[at] = nw;
+            const float d = nw - old;
+            dl = fmaxf(dl, fabsf(d));
+#pragma unroll
+            for (int k = i + 1; k < SEQ_NB; ++k)
+                c[k] += Jb[k][i] * d;
+        }
+    }
+    if (dmax)
+        atomicMax(&dmax[r], __float_as_uint(dl));
+}
+
+void launch_dense_seq_block(const Instance &I, const float *Mold, float *Mnew, float *phi, int ldm, int R, int p0,
+                            int p1, const float *invT, float gamma, uint32_t *dmax, hipStream_t s)
+{
+    const int a0 = p0 & ~3;
+    const int nrt = (p1 - a0 + DBM - 1) / DBM;
+    const int nct = ldm / DBN;
+    const int kpad = (I.N + DBK - 1) / DBK * DBK;
+    k_dense_phase_f32<DWM, DWN, DPF, true><<<nrt * nct, 64 * DWM * DWN, 0, s>>>(
+        I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma, dmax,
+        phi);
+    k_dense_seq_block<<<(R + 63) / 64, 64, 0, s>>>(I.J, I.Np, phi, Mold, Mnew, ldm, R, p0, p1, invT, gamma, dmax);
 }
 
 // ---------------------------------------------------------------------------

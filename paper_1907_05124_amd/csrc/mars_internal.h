@@ -40,6 +40,7 @@ struct Workspace {
     DevBuf runstate;        // paper mode per-run level state
     DevBuf flag;            // small counters
     DevBuf spec;            // Lanczos vectors and coefficients
+    DevBuf phi;             // fields of a sequential block
 };
 
 struct Instance {
@@ -131,6 +132,11 @@ void launch_dense_energy_i8(const Instance &I, const int8_t *Spad, int R, double
 
 // dense
 void launch_dense_init_state(uint64_t seed, int N, int R, int ldm, const float *m0, float *M, hipStream_t s);
+// sequential update: blocks of SEQ_NB spins, each a field product into phi
+// ([Np x ldm]) followed by an in-block pass in index order
+constexpr int SEQ_NB = 64;
+void launch_dense_seq_block(const Instance &I, const float *Mold, float *Mnew, float *phi, int ldm, int R, int p0,
+                            int p1, const float *invT, float gamma, uint32_t *dmax, hipStream_t s);
 void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, int ldm, int R, int p0, int p1,
                             const float *invT, float gamma, uint32_t *dmax, hipStream_t s);
 void launch_dense_round(const float *M, int ldm, int N, int R, int Ke, int8_t *spad, int8_t *spins, float *m_final,
@@ -178,6 +184,7 @@ struct DenseRun {
     int R = 0, ldm = 0, ldr = 0, ldt = 0, kmax = 0, B = 0;
     std::vector<int> pb;  // phase bounds [B + 1]
     bool bf16 = false;
+    bool seq = false;  // sequential update: blocks of SEQ_NB spins
     float gamma = 1.0f;
     double *T0 = nullptr;
     float *table = nullptr;  // [kmax x ldt] 1/T per level and run, -1 past a run's levels

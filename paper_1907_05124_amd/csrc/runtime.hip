@@ -635,8 +635,10 @@ static mars_status check_schedule(const mars_schedule *s, int kind)
         return set_error(MARS_E_ARG, "max_sweeps must be >= 1");
     if (!(s->d_min >= 0.0))
         return set_error(MARS_E_ARG, "d_min must be >= 0");
-    if (s->update != MARS_PHASED && s->update != MARS_JACOBI)
-        return set_error(MARS_E_ARG, "update must be MARS_PHASED or MARS_JACOBI");
+    if (s->update != MARS_PHASED && s->update != MARS_JACOBI && s->update != MARS_SEQUENTIAL)
+        return set_error(MARS_E_ARG, "update must be MARS_PHASED, MARS_JACOBI or MARS_SEQUENTIAL");
+    if (s->update == MARS_SEQUENTIAL && (kind != KIND_DENSE || s->precision != MARS_FP32))
+        return set_error(MARS_E_UNSUPPORTED, "MARS_SEQUENTIAL is implemented for dense instances in MARS_FP32");
     if (kind == KIND_DENSE && s->update == MARS_PHASED && s->phases < 1)
         return set_error(MARS_E_ARG, "phases must be >= 1");
     if (!(s->damping > 0.0 && s->damping <= 1.0))
@@ -722,10 +724,18 @@ mars_status dense_setup(Instance *I, int R, const mars_schedule &sc, uint64_t se
         launch_bf16_init_state(seed, N, R, I->Np, m0, (unsigned short *)w.Ma.p, s);
     else
         launch_dense_init_state(seed, N, R, d.ldm, m0, (float *)w.Ma.p, s);
-    d.B = sc.update == MARS_JACOBI ? 1 : std::min(sc.phases, N);
-    d.pb.assign((size_t)d.B + 1, 0);
-    for (int b = 0; b <= d.B; ++b)
-        d.pb[b] = (int)((long long)b * N / d.B);
+    if (sc.update == MARS_SEQUENTIAL) {
+        d.B = (N + SEQ_NB - 1) / SEQ_NB;
+        d.pb.assign((size_t)d.B + 1, 0);
+        for (int b = 0; b <= d.B; ++b)
+            d.pb[b] = std::min(b * SEQ_NB, N);
+    } else {
+        d.B = sc.update == MARS_JACOBI ? 1 : std::min(sc.phases, N);
+        d.pb.assign((size_t)d.B + 1, 0);
+        for (int b = 0; b <= d.B; ++b)
+            d.pb[b] = (int)((long long)b * N / d.B);
+    }
+    d.seq = sc.update == MARS_SEQUENTIAL;
     d.gamma = (float)sc.damping;
     d.Ma = w.Ma.p;
     d.Mb = w.Mb.p;
@@ -777,11 +787,20 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
     if (bf16 && kmax > 0)
         variant = bf16_phase_variant(*I, (const unsigned short *)cur, (unsigned short *)nxt, I->Np, R, pb[0], pb[1],
                                      table, gamma, s);
+    float *phi = nullptr;
+    if (d.seq) {
+        if ((st = ensure(w.phi, sizeof(float) * (size_t)I->Np * ldm)) != MARS_OK)
+            return st;
+        phi = (float *)w.phi.p;
+    }
     auto sweep = [&](const float *invT, uint32_t *dmax) {
         for (int b = 0; b < B; ++b) {
             if (pb[b + 1] <= pb[b])
                 continue;
-            if (bf16)
+            if (phi)
+                launch_dense_seq_block(*I, (const float *)cur, (float *)nxt, phi, ldm, R, pb[b], pb[b + 1], invT,
+                                       gamma, dmax, s);
+            else if (bf16)
                 launch_dense_phase_bf16(*I, (const unsigned short *)cur, (unsigned short *)nxt, I->Np, R, pb[b],
                                         pb[b + 1], invT, gamma, dmax, variant, s);
             else
@@ -1226,6 +1245,8 @@ mars_status mars_describe(const mars_instance *inst, const mars_schedule *sched,
         int p;
         if (sched && sched->update == MARS_JACOBI)
             p = 1;
+        else if (sched && sched->update == MARS_SEQUENTIAL)
+            p = I->N;
         else if (I->kind == KIND_DENSE)
             p = sched ? std::max(1, std::min(sched->phases, I->N)) : 1;
         else if (I->kind == KIND_LATTICE)

@@ -91,7 +91,7 @@ class Schedule:
     steps: int = 300
     max_sweeps: int = 1
     d_min: float = 1e-4
-    update: str = "phased"  # "phased" | "jacobi"
+    update: str = "phased"  # "phased" | "jacobi" | "sequential" (dense fp32: every spin its own phase)
     phases: int = 2
     damping: float = 1.0
     precision: str = "fp32"  # "fp64" | "fp32" | "bf16" | "fp16"

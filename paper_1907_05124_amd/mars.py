@@ -19,7 +19,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libmars.so")
 
 MARS_GEOMETRIC, MARS_LINEAR = 0, 1
-MARS_PHASED, MARS_JACOBI = 0, 1
+MARS_PHASED, MARS_JACOBI, MARS_SEQUENTIAL = 0, 1, 2
+_UPDATE = {"phased": MARS_PHASED, "jacobi": MARS_JACOBI, "sequential": MARS_SEQUENTIAL}
 MARS_FP32, MARS_FP64, MARS_BF16, MARS_FP16 = 0, 1, 2, 3
 _PRECISION = {"fp32": MARS_FP32, "fp64": MARS_FP64, "bf16": MARS_BF16, "fp16": MARS_FP16}
 
@@ -111,7 +112,7 @@ def make_schedule(sc) -> Schedule:
     s.kind = MARS_GEOMETRIC if sc.kind == "geometric" else MARS_LINEAR
     s.T_lo, s.T_hi, s.T_end, s.c_step = float(sc.T_lo), float(sc.T_hi), float(sc.T_end), float(sc.c_step)
     s.steps, s.max_sweeps, s.d_min = int(sc.steps), int(sc.max_sweeps), float(sc.d_min)
-    s.update = MARS_PHASED if sc.update == "phased" else MARS_JACOBI
+    s.update = _UPDATE[sc.update]
     s.phases, s.damping = int(sc.phases), float(sc.damping)
     s.precision = _PRECISION[sc.precision]
     s.first_level, s.level_count = int(sc.first_level), int(sc.level_count)

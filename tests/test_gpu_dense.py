@@ -289,3 +289,47 @@ def test_dense_exponent_range_pins(kind):
     with M.Instance.from_inputs(inst) as g:
         E = g.energy(torch.from_numpy(S).cuda()).cpu().numpy()
     assert np.array_equal(E, O.energy(inst, S))
+
+
+@pytest.mark.parametrize("N,R,levels,damping,field", [
+    (130, 200, 1, 1.0, 0.0),   # blocks of 64, 64, 2
+    (300, 1031, 1, 1.0, 0.3),  # ragged runs, field
+    (64, 77, 1, 0.5, 0.0),     # one full block, damped
+    (65, 129, 3, 1.0, 0.2),    # a one-spin last block, three levels
+    (517, 300, 2, 1.0, 0.0),
+])
+def test_sequential_parity(N, R, levels, damping, field):
+    """Sequential update (every spin its own phase, in index order; blocks of
+    64 spins with the in-block correction) against the oracle with one phase
+    per spin: fp32 within 1e-5 after one level; over several levels within
+    the oracle-derived trajectory bound (each spin's field depends on every
+    earlier spin's new value, so rounding differences propagate further than
+    in the phased update)."""
+    M = _mars()
+    inst = I.sk_instance(N, 3, field_scale=field)
+    sch = _sched(inst, update="sequential", damping=damping, level_count=levels)
+    announce("dense sequential", N, R, levels, damping, field)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 31, want_m=True)
+        _, phases = g.describe(sch)
+    assert phases == N
+    ref = O.solve(inst, R, sch, 31, run_count=R)
+    if levels == 1:
+        err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
+        assert err <= TOL_FP32, err
+    else:
+        within = check_trajectory(out["m"].cpu().numpy(), inst, R, sch, 31, ref, "fp32")
+        print("runs within 1e-5: %.3f" % within)
+
+
+def test_sequential_unsupported_forms():
+    M = _mars()
+    inst = I.sk_instance(100, 3)
+    with M.Instance.from_inputs(inst) as g:
+        with pytest.raises(M.MarsError) as e:
+            g.solve_ex(16, _sched(inst, update="sequential", precision="bf16"), 1)
+        assert e.value.status == 8
+    with M.Instance.from_inputs(I.lattice_instance((8, 8), 1)) as g:
+        with pytest.raises(M.MarsError) as e:
+            g.solve_ex(16, _sched(I.lattice_instance((8, 8), 1), update="sequential", precision="fp32"), 1)
+        assert e.value.status == 8

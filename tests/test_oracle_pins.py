@@ -426,3 +426,30 @@ def test_phased_beats_jacobi_on_lattice():
     N = w.instance.N
     assert a["energy"].mean() / N < -2.4
     assert abs(b["energy"].mean() / N) < 0.5
+
+
+def test_sequential_is_one_phase_per_spin():
+    """The sequential update (dense) is the phased update with every spin its
+    own phase in index order: the oracle's phase map and a one-level result
+    equal those of phases = N."""
+    from oracle import oracle as O
+    from paper_1907_05124_amd import inputs as I
+
+    inst = I.sk_instance(24, 3, field_scale=0.3)
+    seq = I.Schedule(steps=3, phases=2, update="sequential")
+    ph, n = O.phases(inst, seq)
+    assert n == 24 and list(ph) == list(range(24))
+    a = O.solve(inst, 5, seq, 7, run_count=5)
+    b = O.solve(inst, 5, seq.replace(update="phased", phases=24), 7, run_count=5)
+    assert np.array_equal(a["m"], b["m"])
+    # one level written out as a plain Gauss-Seidel loop in index order
+    one = seq.replace(level_count=1, precision="fp64")
+    got = O.solve(inst, 5, one, 7, run_count=5)
+    J = inst.J.astype(np.float64)
+    h = inst.h.astype(np.float64)
+    m = O.initial_m(7, 5, 24).astype(np.float64)
+    T0 = got["T0"]
+    for r in range(5):
+        for i in range(24):
+            m[i, r] = math.tanh((sum(J[i, j] * m[j, r] for j in range(24)) + h[i] / 2) / T0[r])
+    assert np.allclose(got["m"], m, rtol=0, atol=1e-12)
