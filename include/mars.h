@@ -238,8 +238,9 @@ mars_status mars_auto_temperatures(mars_instance *inst, int32_t steps, uint64_t 
  * Results equal mars_solve_async's for the same arguments bit for bit.
  *
  * mars_batch_create: stream is a hipStream_t (NULL: the default stream) on
- *   the current device; the batch owns no device memory.  Errors: MARS_E_ARG
- *   (out NULL), MARS_E_OOM.
+ *   the current device; the batch owns 16 level counters in device memory
+ *   and its step graph.  Errors: MARS_E_ARG (out NULL), MARS_E_OOM,
+ *   MARS_E_DEVICE.
  * mars_batch_add: enqueues the member's set-up (its workspace, starting
  *   temperatures, level table, initial state) on the batch stream; it joins
  *   at the next step.  inst: a dense instance on the batch's device, owned by
@@ -252,13 +253,18 @@ mars_status mars_auto_temperatures(mars_instance *inst, int32_t steps, uint64_t 
  *   device, or the batch already holds 16 members), MARS_E_OOM, MARS_E_DEVICE.
  * mars_batch_step: enqueues up to `sweeps` sweeps of every member; a member
  *   that reaches its last level is rounded and scored, its outputs are
- *   copied, and it leaves.  finished_tags: HOST int64 [cap] receiving the tags
- *   of the members that left during this call (*n_finished of them, never
- *   more than cap: a finished member beyond that stays, without sweeping,
- *   and leaves at a later call; sweeps = 0 only retires); *n_active: members
- *   still in the batch.  Outputs of a finished member are valid once
- *   the stream has passed the work enqueued by the call.  Errors: MARS_E_ARG,
- *   MARS_E_DEVICE.
+ *   copied, and it leaves.  On a non-NULL stream the step's launches are
+ *   captured once as a graph and replayed by later steps while no member
+ *   joins or leaves and `sweeps` is unchanged (MARS_BATCH_GRAPH=0 in the
+ *   environment at mars_batch_create launches sweep by sweep instead); a
+ *   member that finishes inside a replayed step leaves at the step's end.
+ *   Results are the same either way.  finished_tags: HOST int64 [cap]
+ *   receiving the tags of the members that left during this call
+ *   (*n_finished of them, never more than cap: a finished member beyond that
+ *   stays, without sweeping, and leaves at a later call; sweeps = 0 only
+ *   retires); *n_active: members still in the batch.  Outputs of a finished
+ *   member are valid once the stream has passed the work enqueued by the
+ *   call.  Errors: MARS_E_ARG, MARS_E_DEVICE.
  * mars_batch_destroy: waits for the batch stream and releases the batch and
  *   every member still in it (their outputs are not written).  NULL is a
  *   no-op.  An instance is destroyed only after its member has finished or
