@@ -31,8 +31,8 @@ PEAK = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0, "fp32_valu": 78.
 # (KiB per dispatch, SK2000 workload), scaled by the counters' reading of a
 # plain 256 MiB copy.  Valid only for the kernel source they were taken on.
 TRAFFIC_RECORD = {
-    "fp32": {"source": "paper_1907_05124_amd/csrc/dense_phase.h", "sha256_prefix": "f9fb3b74ef6c09ae",
-             "workload": "sk2000", "fetch_kib": 54875.6, "write_kib": 16000.0,
+    "fp32": {"source": "paper_1907_05124_amd/csrc/dense_phase.h", "sha256_prefix": "4be37f4594fd5dee",
+             "workload": "sk2000", "fetch_kib": 54899.4, "write_kib": 16000.0,
              "fetch_scale": 2.0, "write_scale": 1.0, "summary": "profiles/k_dense_phase_f32_sk2000.md"},
     "bf16": {"source": "paper_1907_05124_amd/csrc/dense_phase_bf16.h", "sha256_prefix": "237f59c1c1e9c87f",
              "workload": "sk2000", "fetch_kib": 26428.9, "write_kib": 8256.0,
