@@ -12,6 +12,7 @@
 //    writes a second copy and swaps.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common_device.h"
 #include "lds_state.h"
@@ -104,12 +105,13 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
         // the runs' level state, advanced at the end of the previous sweep
         C scale[VEC];
         bool done[VEC];
-        bool any = false;
+        bool any = false, all = true;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            scale[e] = run_scale<C>(rsl[q0 + e]);
+            scale[e] = run_tscale<C>(rsl[q0 + e]);
             done[e] = rsl[q0 + e].done != 0;
             any |= !done[e];
+            all &= !done[e];
         }
         if (!__syncthreads_or(any))
             break;
@@ -121,8 +123,11 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
         unsigned char *wb = reinterpret_cast<unsigned char *>(JAC ? m2 : m) + q0 * sizeof(S);
         // update site v at LDS byte offset vb (from the thread's run slot);
         // o*: byte offsets of its neighbours along +x, -x, +y, -y, +z, -z
-        auto site = [&](int v, uint32_t vb, uint32_t oxp, uint32_t oxm, uint32_t oyp, uint32_t oym, uint32_t ozp,
-                        uint32_t ozm) {
+        // LIVE: every run of the thread is still annealing, so (undamped, no
+        // convergence tracking) the old value is not needed
+        auto site = [&](auto live, int v, uint32_t vb, uint32_t oxp, uint32_t oxm, uint32_t oyp, uint32_t oym,
+                        uint32_t ozp, uint32_t ozm) {
+            constexpr bool FAST = decltype(live)::value && !DAMP && !TRACKD;
             const uint32_t b = bonds[(unsigned)v];
             C phi[VEC];
             if constexpr (sizeof(S) == 2 && VEC == 2) {
@@ -194,11 +199,18 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
                 for (int e = 0; e < VEC; ++e)
                     phi[e] += hh;
             }
-            const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + vb));
             Pack<S, VEC> nw;
+            if constexpr (FAST) {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    nw.v[e] = LStore<S>::st(l_tanh_run(phi[e], scale[e]));
+                lds_put<S, VEC>(reinterpret_cast<S *>(wb + vb), nw);
+                return;
+            }
+            const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + vb));
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                const C th = l_tanh(l_apply(phi[e], scale[e]));
+                const C th = l_tanh_run(phi[e], scale[e]);
                 const C o = LStore<S>::ld(old.v[e]);
                 C n = DAMP ? ((C)1 - g) * o + g * th : th;
                 n = done[e] ? o : n;  // a finished run keeps its state
@@ -208,65 +220,71 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
             }
             lds_put<S, VEC>(reinterpret_cast<S *>(wb + vb), nw);
         };
-        for (int c = 0; c < (JAC ? 1 : 2); ++c) {
-            if (cols && !JAC && (kz & 1) == 0) {
-                // even walk step: the thread's x parity is fixed for the whole
-                // walk, so its site, x and y offsets are constants; only the
-                // first and last planes of the lattice wrap along z
-                const int p = (c + cy + cz0) & 1;
-                int v = L0 * (cy + L1 * cz0) + 2 * xh + p;
-                uint32_t vb = ob(v);
-                const int dv = kz * plane;
-                const uint32_t dvb = opaque(ob(dv));
-                const uint32_t xp = opaque(p ? oxp1 : oxp0), xm = opaque(p ? oxm1 : oxm0);
-                const uint32_t yp = opaque(cyp), ym = opaque(cym);
-                const uint32_t zp = opaque(ob(plane)), zm = opaque(ob(-plane));
-                for (int z = cz0; z < L2; z += kz, v += dv, vb += dvb) {
-                    if (z > 0 && z + 1 < L2) {
-                        site(v, vb, xp, xm, yp, ym, zp, zm);
-                    } else {
-                        const uint32_t ozp = z + 1 < L2 ? zp : ob(plane - vol);
-                        const uint32_t ozm = z > 0 ? zm : ob(vol - plane);
-                        site(v, vb, xp, xm, yp, ym, ozp, ozm);
+        auto sweep = [&](auto live) {
+            for (int c = 0; c < (JAC ? 1 : 2); ++c) {
+                if (cols && !JAC && (kz & 1) == 0) {
+                    // even walk step: the thread's x parity is fixed for the whole
+                    // walk, so its site, x and y offsets are constants; only the
+                    // first and last planes of the lattice wrap along z
+                    const int p = (c + cy + cz0) & 1;
+                    int v = L0 * (cy + L1 * cz0) + 2 * xh + p;
+                    uint32_t vb = ob(v);
+                    const int dv = kz * plane;
+                    const uint32_t dvb = opaque(ob(dv));
+                    const uint32_t xp = opaque(p ? oxp1 : oxp0), xm = opaque(p ? oxm1 : oxm0);
+                    const uint32_t yp = opaque(cyp), ym = opaque(cym);
+                    const uint32_t zp = opaque(ob(plane)), zm = opaque(ob(-plane));
+                    for (int z = cz0; z < L2; z += kz, v += dv, vb += dvb) {
+                        if (z > 0 && z + 1 < L2) {
+                            site(live, v, vb, xp, xm, yp, ym, zp, zm);
+                        } else {
+                            const uint32_t ozp = z + 1 < L2 ? zp : ob(plane - vol);
+                            const uint32_t ozm = z > 0 ? zm : ob(vol - plane);
+                            site(live, v, vb, xp, xm, yp, ym, ozp, ozm);
+                        }
+                    }
+                } else if (cols) {
+                    // site and byte offset carried along the column
+                    int v0 = L0 * (cy + L1 * cz0) + 2 * xh;
+                    uint32_t vb0 = ob(v0);
+                    const int dv = kz * plane;
+                    const uint32_t dvb = ob(dv);
+                    for (int z = cz0; z < L2; z += kz, v0 += dv, vb0 += dvb) {
+                        const uint32_t ozp = ob(z + 1 < L2 ? plane : plane - vol);
+                        const uint32_t ozm = ob(z > 0 ? -plane : vol - plane);
+    #pragma unroll
+                        for (int pp = 0; pp < (JAC ? 2 : 1); ++pp) {
+                            const int p = JAC ? pp : ((c + cy + z) & 1);
+                            site(live, v0 + p, vb0 + (p ? oxp0 : 0u), p ? oxp1 : oxp0, p ? oxm1 : oxm0, cyp, cym, ozp, ozm);
+                        }
+                    }
+                } else {
+                    int y = row0 % L1, z = row0 / L1;
+                    for (int rw = row0; rw < nrows; rw += drow) {
+                        const uint32_t oyp = ob(y + 1 < L1 ? L0 : L0 - plane), oym = ob(y > 0 ? -L0 : plane - L0);
+                        const uint32_t ozp = ob(z + 1 < L2 ? plane : plane - vol);
+                        const uint32_t ozm = ob(z > 0 ? -plane : vol - plane);
+    #pragma unroll
+                        for (int pp = 0; pp < (JAC ? 2 : 1); ++pp) {
+                            const int p = JAC ? pp : ((c + y + z) & 1);
+                            const int v = L0 * rw + 2 * xh + p;
+                            site(live, v, ob(v), p ? oxp1 : oxp0, p ? oxm1 : oxm0, oyp, oym, ozp, ozm);
+                        }
+                        y += dy;
+                        z += dz;
+                        if (y >= L1) {
+                            y -= L1;
+                            ++z;
+                        }
                     }
                 }
-            } else if (cols) {
-                // site and byte offset carried along the column
-                int v0 = L0 * (cy + L1 * cz0) + 2 * xh;
-                uint32_t vb0 = ob(v0);
-                const int dv = kz * plane;
-                const uint32_t dvb = ob(dv);
-                for (int z = cz0; z < L2; z += kz, v0 += dv, vb0 += dvb) {
-                    const uint32_t ozp = ob(z + 1 < L2 ? plane : plane - vol);
-                    const uint32_t ozm = ob(z > 0 ? -plane : vol - plane);
-#pragma unroll
-                    for (int pp = 0; pp < (JAC ? 2 : 1); ++pp) {
-                        const int p = JAC ? pp : ((c + cy + z) & 1);
-                        site(v0 + p, vb0 + (p ? oxp0 : 0u), p ? oxp1 : oxp0, p ? oxm1 : oxm0, cyp, cym, ozp, ozm);
-                    }
-                }
-            } else {
-                int y = row0 % L1, z = row0 / L1;
-                for (int rw = row0; rw < nrows; rw += drow) {
-                    const uint32_t oyp = ob(y + 1 < L1 ? L0 : L0 - plane), oym = ob(y > 0 ? -L0 : plane - L0);
-                    const uint32_t ozp = ob(z + 1 < L2 ? plane : plane - vol);
-                    const uint32_t ozm = ob(z > 0 ? -plane : vol - plane);
-#pragma unroll
-                    for (int pp = 0; pp < (JAC ? 2 : 1); ++pp) {
-                        const int p = JAC ? pp : ((c + y + z) & 1);
-                        const int v = L0 * rw + 2 * xh + p;
-                        site(v, ob(v), p ? oxp1 : oxp0, p ? oxm1 : oxm0, oyp, oym, ozp, ozm);
-                    }
-                    y += dy;
-                    z += dz;
-                    if (y >= L1) {
-                        y -= L1;
-                        ++z;
-                    }
-                }
+                __syncthreads();
             }
-            __syncthreads();
-        }
+        };
+        if (all)
+            sweep(std::true_type{});
+        else
+            sweep(std::false_type{});
         if (JAC) {
             S *tmp = m;
             m = m2;

@@ -173,11 +173,28 @@ struct RunState {
 constexpr size_t RUN_AREA_BYTES = sizeof(RunState) + sizeof(uint32_t);
 static_assert(RUN_AREA_BYTES <= RUN_AREA_MAX, "per-run LDS area exceeds the launcher's reservation");
 
+// tanh(Phi / T) from a per-run factor ts (run_tscale): fp32 folds the
+// exp2 constant of l_tanh into the factor, ts = 2 log2(e) / T, saving a
+// multiply per update; fp64 divides by T and takes the libm tanh
+__device__ inline float l_tanh_run(float phi, float ts)
+{
+    const float e = __builtin_amdgcn_exp2f(fabsf(phi) * ts);
+    const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+    return copysignf(t, phi);
+}
+__device__ inline double l_tanh_run(double phi, double T) { return tanh(phi / T); }
+
 template <typename C>
 __device__ inline C run_scale(const RunState &r);
 template <>
 __device__ inline float run_scale<float>(const RunState &r) { return r.invT32; }
 template <>
 __device__ inline double run_scale<double>(const RunState &r) { return r.T; }
+template <typename C>
+__device__ inline C run_tscale(const RunState &r);
+template <>
+__device__ inline float run_tscale<float>(const RunState &r) { return r.invT32 * 2.8853900817779268f; }
+template <>
+__device__ inline double run_tscale<double>(const RunState &r) { return r.T; }
 
 }  // namespace mars
