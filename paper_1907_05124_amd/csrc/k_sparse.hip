@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 #include "common_device.h"
 #include "lds_state.h"
@@ -91,12 +92,13 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
         // the runs' level state, advanced at the end of the previous sweep
         C scale[VEC];
         bool done[VEC];
-        bool any = false;
+        bool any = false, all = true;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-            scale[e] = run_scale<C>(rsl[q0 + e]);
+            scale[e] = run_tscale<C>(rsl[q0 + e]);
             done[e] = rsl[q0 + e].done != 0;
             any |= !done[e];
+            all &= !done[e];
         }
         if (!__syncthreads_or(any))
             break;
@@ -104,74 +106,90 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
             dloc[e] = 0;
-        const int nph = JAC ? 1 : a.nphase;
-        for (int c = 0; c < nph; ++c) {
-            // the synchronous sweep visits every slot (padding slots are inert:
-            // no terms, zero field, state 0)
-            const int sb = JAC ? 0 : a.cls[2 * c];
-            const int sn = JAC ? ns : a.cls[2 * c + 1];
-            const unsigned char *mb = reinterpret_cast<const unsigned char *>(m) + q0 * sizeof(S);
-            unsigned char *wb = reinterpret_cast<unsigned char *>(JAC ? m2 : m) + q0 * sizeof(S);
-            // the slice record (offset, width) of the thread's next slot is
-            // read while the current one is computed (index clamped to the
-            // class's last slot: in bounds, unused past the end)
-            const int2 *rec = reinterpret_cast<const int2 *>(meta);
-            const unsigned last = (unsigned)min(sb + max(sn, 1) - 1, ns - 1);
-            int2 rc = rec[min((unsigned)(sb + tq), last) / SELL_H];
-            for (int it = tq; it < sn; it += Tq) {
-                const int slot = sb + it;
-                const int2 rn = rec[min((unsigned)(slot + Tq), last) / SELL_H];
-                const int off = rc.x;
-                const int w = rc.y;
-                rc = rn;
-                const uint32_t *cp = colsell + off + ((unsigned)slot % SELL_H);
-                C phi[VEC];
-#pragma unroll
-                for (int e = 0; e < VEC; ++e)
-                    phi[e] = 0;
-                // w is a multiple of SELL_W: whole groups, no remainder loop
-                for (int j = 0; j < w; j += SELL_W) {
-                    uint32_t cb[SELL_W];
-#pragma unroll
-                    for (int u = 0; u < SELL_W; ++u)
-                        cb[u] = cp[(j + u) * SELL_H];
-#pragma unroll
-                    for (int u = 0; u < SELL_W; ++u) {
-                        const C wt = entry_weight<C, UNIT>(cb[u]);
-                        const Pack<S, VEC> t =
-                            lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((cb[u] & 0xffffffu) << lgs)));
-#pragma unroll
-                        for (int e = 0; e < VEC; ++e)
-                            phi[e] += wt * LStore<S>::ld(t.v[e]);
-                    }
-                }
-                if (HAS_H) {
-                    C hh;
-                    if constexpr (sizeof(C) == 8)
-                        hh = a.hhalf64[slot];
-                    else
-                        hh = a.hhalf32[slot];
-#pragma unroll
+        auto sweep = [&](auto live) {
+            constexpr bool FAST = decltype(live)::value && !DAMP && !TRACKD;
+            const int nph = JAC ? 1 : a.nphase;
+            for (int c = 0; c < nph; ++c) {
+                // the synchronous sweep visits every slot (padding slots are inert:
+                // no terms, zero field, state 0)
+                const int sb = JAC ? 0 : a.cls[2 * c];
+                const int sn = JAC ? ns : a.cls[2 * c + 1];
+                const unsigned char *mb = reinterpret_cast<const unsigned char *>(m) + q0 * sizeof(S);
+                unsigned char *wb = reinterpret_cast<unsigned char *>(JAC ? m2 : m) + q0 * sizeof(S);
+                // the slice record (offset, width) of the thread's next slot is
+                // read while the current one is computed (index clamped to the
+                // class's last slot: in bounds, unused past the end)
+                const int2 *rec = reinterpret_cast<const int2 *>(meta);
+                const unsigned last = (unsigned)min(sb + max(sn, 1) - 1, ns - 1);
+                int2 rc = rec[min((unsigned)(sb + tq), last) / SELL_H];
+                for (int it = tq; it < sn; it += Tq) {
+                    const int slot = sb + it;
+                    const int2 rn = rec[min((unsigned)(slot + Tq), last) / SELL_H];
+                    const int off = rc.x;
+                    const int w = rc.y;
+                    rc = rn;
+                    const uint32_t *cp = colsell + off + ((unsigned)slot % SELL_H);
+                    C phi[VEC];
+    #pragma unroll
                     for (int e = 0; e < VEC; ++e)
-                        phi[e] += hh;
+                        phi[e] = 0;
+                    // w is a multiple of SELL_W: whole groups, no remainder loop
+                    for (int j = 0; j < w; j += SELL_W) {
+                        uint32_t cb[SELL_W];
+    #pragma unroll
+                        for (int u = 0; u < SELL_W; ++u)
+                            cb[u] = cp[(j + u) * SELL_H];
+    #pragma unroll
+                        for (int u = 0; u < SELL_W; ++u) {
+                            const C wt = entry_weight<C, UNIT>(cb[u]);
+                            const Pack<S, VEC> t =
+                                lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((cb[u] & 0xffffffu) << lgs)));
+    #pragma unroll
+                            for (int e = 0; e < VEC; ++e)
+                                phi[e] += wt * LStore<S>::ld(t.v[e]);
+                        }
+                    }
+                    if (HAS_H) {
+                        C hh;
+                        if constexpr (sizeof(C) == 8)
+                            hh = a.hhalf64[slot];
+                        else
+                            hh = a.hhalf32[slot];
+    #pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            phi[e] += hh;
+                    }
+                    const uint32_t o_slot = (uint32_t)slot << lgs;
+                    Pack<S, VEC> nw;
+                    if constexpr (FAST) {
+                        // every run of the thread still anneals, undamped, no
+                        // convergence tracking: the old value is not needed
+    #pragma unroll
+                        for (int e = 0; e < VEC; ++e)
+                            nw.v[e] = LStore<S>::st(l_tanh_run(phi[e], scale[e]));
+                        lds_put<S, VEC>(reinterpret_cast<S *>(wb + o_slot), nw);
+                        continue;
+                    }
+                    const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + o_slot));
+    #pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const C th = l_tanh_run(phi[e], scale[e]);
+                        const C o = LStore<S>::ld(old.v[e]);
+                        C n = DAMP ? ((C)1 - g) * o + g * th : th;
+                        n = done[e] ? o : n;  // a finished run keeps its state
+                        nw.v[e] = done[e] ? old.v[e] : LStore<S>::st(n);
+                        const C dd = n > o ? n - o : o - n;
+                        dloc[e] = dd > dloc[e] ? dd : dloc[e];
+                    }
+                    lds_put<S, VEC>(reinterpret_cast<S *>(wb + o_slot), nw);
                 }
-                const uint32_t o_slot = (uint32_t)slot << lgs;
-                const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + o_slot));
-                Pack<S, VEC> nw;
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) {
-                    const C th = l_tanh(l_apply(phi[e], scale[e]));
-                    const C o = LStore<S>::ld(old.v[e]);
-                    C n = DAMP ? ((C)1 - g) * o + g * th : th;
-                    n = done[e] ? o : n;  // a finished run keeps its state
-                    nw.v[e] = done[e] ? old.v[e] : LStore<S>::st(n);
-                    const C dd = n > o ? n - o : o - n;
-                    dloc[e] = dd > dloc[e] ? dd : dloc[e];
-                }
-                lds_put<S, VEC>(reinterpret_cast<S *>(wb + o_slot), nw);
+                __syncthreads();
             }
-            __syncthreads();
-        }
+        };
+        if (all)
+            sweep(std::true_type{});
+        else
+            sweep(std::false_type{});
         if (JAC) {
             S *tmp = m;
             m = m2;
