@@ -158,9 +158,10 @@ def copy_calibration():
 
 
 def served(args):
-    """Served mixed stream: a capacity pass (all requests at t = 0), then a
-    Poisson pass at 70 % of that capacity; latency is arrival to result."""
-    import numpy as np
+    """Served mixed stream: a capacity pass (all requests at t = 0), then
+    Poisson passes at the given fractions of that capacity (default 0.7);
+    latency is arrival to result.  The same instances serve every pass (the
+    arrival times differ)."""
     import torch
 
     from paper_1907_05124_amd import serve as S
@@ -168,33 +169,46 @@ def served(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     server = S.MarsServer(max_active=8, n_streams=4, batching=not args.no_batching)
+    fracs = [float(x) for x in args.rates.split(",")]
+
+    base = S.mixed_stream(args.requests, 1e9, seed=args.seed)
+    for k, r in enumerate(base):  # synthetic inputs are generated before the clock starts
+        r.instance = r.materialize()
+        if (k + 1) % 200 == 0:
+            log("materialised %d / %d instances" % (k + 1, len(base)))
 
     def make(rate):
         reqs = S.mixed_stream(args.requests, rate, seed=args.seed)
-        for r in reqs:  # synthetic inputs are generated before the clock starts
-            r.instance = r.materialize()
+        for r, b in zip(reqs, base):
+            assert r.runs == b.runs and r.N == b.N
+            r.instance = b.instance
         return reqs
 
     warm = S.mixed_stream(4, 1e9, seed=args.seed + 7, n_hi=500)
     server.run(warm)
-    cap_reqs = make(1e9)
-    log("capacity pass: %d requests" % len(cap_reqs))
-    _, cap = server.run(cap_reqs)
-    rate = 0.7 * cap["requests"] / cap["makespan_s"]
-    log("capacity", cap, "-> offered rate %.2f req/s" % rate)
-    load_reqs = make(rate)
-    _, st = server.run(load_reqs)
-    log("load pass", st)
+    log("capacity pass: %d requests" % len(base))
+    _, cap = server.run(base, progress=log)
+    capacity = cap["requests"] / cap["makespan_s"]
+    log("capacity", cap, "-> %.2f req/s" % capacity)
+    sweep = []
+    for f in fracs:
+        rate = f * capacity
+        _, st = server.run(make(rate), progress=log)
+        log("load pass at %.2f of capacity (%.2f req/s)" % (f, rate), st)
+        sweep.append({"fraction_of_capacity": f, "offered_rate_per_s": rate, **st})
+    head = next((x for x in sweep if abs(x["fraction_of_capacity"] - 0.7) < 1e-9), sweep[-1])
     line = {
-        "metric": METRIC, "value": st["spin_updates_per_s"], "unit": "spin-updates/s", "n_gpus": 1,
-        "steps": st["requests"], "warmup": len(warm), "ms_per_step": st["makespan_s"] * 1e3 / max(1, st["requests"]),
+        "metric": METRIC, "value": head["spin_updates_per_s"], "unit": "spin-updates/s", "n_gpus": 1,
+        "steps": head["requests"], "warmup": len(warm),
+        "ms_per_step": head["makespan_s"] * 1e3 / max(1, head["requests"]),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (dense) / f32 (sparse)",
         "data": "synthetic",
-        "config": {"workload": "served", "description": DESCRIPTION["served"], "requests": st["requests"],
-                   "offered_rate_per_s": rate, "batching": not args.no_batching,
+        "config": {"workload": "served", "description": DESCRIPTION["served"], "requests": head["requests"],
+                   "offered_rate_per_s": head["offered_rate_per_s"],
+                   "fraction_of_capacity": head["fraction_of_capacity"], "batching": not args.no_batching,
                    "parallelism": "single GPU, concurrent streams"},
-        "latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"]},
-        "capacity": cap, "load": st, "roofline": None, "cpu_baseline": None,
+        "latency_ms": {"p50": head["latency_p50_ms"], "p99": head["latency_p99_ms"]},
+        "capacity": cap, "load_sweep": sweep, "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 
@@ -209,6 +223,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16", "fp16"],
                     help="override the workload's arithmetic form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rates", default="0.7",
+                    help="served workload: offered loads as fractions of the measured capacity, comma separated")
     ap.add_argument("--no-batching", action="store_true",
                     help="served workload: run every request alone on the stream pool")
     ap.add_argument("--requests", type=int, default=200, help="served workload: number of requests")

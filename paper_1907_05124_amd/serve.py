@@ -224,9 +224,11 @@ class MarsServer:
         self.batch_sweeps = int(batch_sweeps)
         self.batch_stream = torch.cuda.Stream() if batching else None
 
-    def run(self, requests, time_scale: float = 1.0, verbose: bool = False):
+    def run(self, requests, time_scale: float = 1.0, verbose: bool = False, progress=None,
+            progress_every_s: float = 30.0):
         """Serve `requests` (arrival times in seconds, scaled by time_scale);
-        returns (completions, stats)."""
+        returns (completions, stats).  `progress(msg)`, if given, is called
+        every progress_every_s seconds with the number of requests served."""
         torch, M = self.torch, self.M
         cap = self.M.Batch.MAX_MEMBERS if self.batching else 0
         # the batch's members have slots of their own beside the stream pool's
@@ -242,8 +244,12 @@ class MarsServer:
         stream_load = [0] * len(self.streams)
         peak_running = peak_batch = 0
         t0 = time.perf_counter()
+        last_report = t0
         try:
             while sched.queue or running:
+                if progress is not None and time.perf_counter() - last_report >= progress_every_s:
+                    last_report = time.perf_counter()
+                    progress("served %d / %d requests, %d running" % (len(done), len(requests), len(running)))
                 now = (time.perf_counter() - t0) / time_scale
                 progressed = False
                 # retire finished requests
