@@ -172,10 +172,15 @@ def served(args):
     fracs = [float(x) for x in args.rates.split(",")]
 
     base = S.mixed_stream(args.requests, 1e9, seed=args.seed)
-    for k, r in enumerate(base):  # synthetic inputs are generated before the clock starts
-        r.instance = r.materialize()
-        if (k + 1) % 200 == 0:
-            log("materialised %d / %d instances" % (k + 1, len(base)))
+    # synthetic inputs are generated before the clock starts (threads: the
+    # generators spend their time in numpy, outside the interpreter lock)
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as pool:
+        for k, inst in enumerate(pool.map(lambda r: r.materialize(), base)):
+            base[k].instance = inst
+            if (k + 1) % 200 == 0:
+                log("materialised %d / %d instances" % (k + 1, len(base)))
 
     def make(rate):
         reqs = S.mixed_stream(args.requests, rate, seed=args.seed)
