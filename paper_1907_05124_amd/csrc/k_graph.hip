@@ -73,6 +73,7 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     a.perm = I.perm;
     a.sl_meta = I.sl_meta;
     a.colsell = I.colsell;
+    a.long_rows = (!lat && I.nnz >= 16LL * N) ? 1 : 0;
     a.cls = I.cls;
     a.dim = I.dim;
     a.L0 = I.L[0];

@@ -85,6 +85,7 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
     for (int sz = (int)sizeof(S); sz > 1; sz >>= 1)
         ++lgs;
     const uint32_t *__restrict__ colsell = a.colsell;
+    const bool long_rows = a.long_rows != 0;
     const int32_t *__restrict__ meta = a.sl_meta;
 
     __syncthreads();
@@ -130,23 +131,47 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                     rc = rn;
                     const uint32_t *cp = colsell + off + ((unsigned)slot % SELL_H);
                     C phi[VEC];
-    #pragma unroll
+#pragma unroll
                     for (int e = 0; e < VEC; ++e)
                         phi[e] = 0;
                     // w is a multiple of SELL_W: whole groups, no remainder loop
-                    for (int j = 0; j < w; j += SELL_W) {
-                        uint32_t cb[SELL_W];
-    #pragma unroll
-                        for (int u = 0; u < SELL_W; ++u)
-                            cb[u] = cp[(j + u) * SELL_H];
-    #pragma unroll
+                    auto group = [&](const uint32_t *cb) {
+#pragma unroll
                         for (int u = 0; u < SELL_W; ++u) {
                             const C wt = entry_weight<C, UNIT>(cb[u]);
                             const Pack<S, VEC> t =
                                 lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((cb[u] & 0xffffffu) << lgs)));
-    #pragma unroll
+#pragma unroll
                             for (int e = 0; e < VEC; ++e)
                                 phi[e] += wt * LStore<S>::ld(t.v[e]);
+                        }
+                    };
+                    if (!long_rows) {
+                        for (int j = 0; j < w; j += SELL_W) {
+                            uint32_t cb[SELL_W];
+#pragma unroll
+                            for (int u = 0; u < SELL_W; ++u)
+                                cb[u] = cp[(j + u) * SELL_H];
+                            group(cb);
+                        }
+                    } else {
+                        // long rows (high average degree): the next group's
+                        // entries are read while the current group is summed
+                        // (the last group re-reads itself: in bounds, unused)
+                        uint32_t cb[SELL_W];
+#pragma unroll
+                        for (int u = 0; u < SELL_W; ++u)
+                            cb[u] = cp[u * SELL_H];
+                        for (int j = 0; j < w; j += SELL_W) {
+                            const int jn = j + SELL_W < w ? j + SELL_W : j;
+                            uint32_t nx[SELL_W];
+#pragma unroll
+                            for (int u = 0; u < SELL_W; ++u)
+                                nx[u] = cp[(jn + u) * SELL_H];
+                            group(cb);
+#pragma unroll
+                            for (int u = 0; u < SELL_W; ++u)
+                                cb[u] = nx[u];
                         }
                     }
                     if (HAS_H) {
@@ -155,7 +180,7 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                             hh = a.hhalf64[slot];
                         else
                             hh = a.hhalf32[slot];
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < VEC; ++e)
                             phi[e] += hh;
                     }
@@ -164,14 +189,14 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                     if constexpr (FAST) {
                         // every run of the thread still anneals, undamped, no
                         // convergence tracking: the old value is not needed
-    #pragma unroll
+#pragma unroll
                         for (int e = 0; e < VEC; ++e)
                             nw.v[e] = LStore<S>::st(l_tanh_run(phi[e], scale[e]));
                         lds_put<S, VEC>(reinterpret_cast<S *>(wb + o_slot), nw);
                         continue;
                     }
                     const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + o_slot));
-    #pragma unroll
+#pragma unroll
                     for (int e = 0; e < VEC; ++e) {
                         const C th = l_tanh_run(phi[e], scale[e]);
                         const C o = LStore<S>::ld(old.v[e]);

@@ -223,6 +223,7 @@ struct GraphArgs {
     const int32_t *sl_meta;
     const uint32_t *colsell;
     const int32_t *cls;
+    int long_rows;  // sparse: average degree >= 16, entry groups are read one ahead
     // lattice
     int dim, L0, L1, L2;
     const uint8_t *bondbits;
