@@ -154,24 +154,30 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                                 cb[u] = cp[(j + u) * SELL_H];
                             group(cb);
                         }
-                    } else {
-                        // long rows (high average degree): the next group's
-                        // entries are read while the current group is summed
-                        // (the last group re-reads itself: in bounds, unused)
-                        uint32_t cb[SELL_W];
+                    } else if (w > 0) {
+                        // long rows (high average degree): entry groups are
+                        // read two groups ahead of the one being summed (past
+                        // the row's end the last group is re-read: in bounds,
+                        // unused; a slice without entries reads nothing)
+                        const int wl = w - SELL_W;  // start of the last group
+                        uint32_t cb[SELL_W], n1[SELL_W];
 #pragma unroll
-                        for (int u = 0; u < SELL_W; ++u)
+                        for (int u = 0; u < SELL_W; ++u) {
                             cb[u] = cp[u * SELL_H];
+                            n1[u] = cp[(min(SELL_W, wl) + u) * SELL_H];
+                        }
                         for (int j = 0; j < w; j += SELL_W) {
-                            const int jn = j + SELL_W < w ? j + SELL_W : j;
-                            uint32_t nx[SELL_W];
+                            const int j2 = min(j + 2 * SELL_W, wl);
+                            uint32_t n2[SELL_W];
 #pragma unroll
                             for (int u = 0; u < SELL_W; ++u)
-                                nx[u] = cp[(jn + u) * SELL_H];
+                                n2[u] = cp[(j2 + u) * SELL_H];
                             group(cb);
 #pragma unroll
-                            for (int u = 0; u < SELL_W; ++u)
-                                cb[u] = nx[u];
+                            for (int u = 0; u < SELL_W; ++u) {
+                                cb[u] = n1[u];
+                                n1[u] = n2[u];
+                            }
                         }
                     }
                     if (HAS_H) {

@@ -41,7 +41,16 @@ CASES = {
     "er_unit": lambda: I.er_instance(300, 6, p=0.05, weights="unit"),
     "er_field": lambda: _with_field(I.er_instance(200, 7, p=0.05, weights="pm1"), 0.4),
     "lat_field": lambda: _with_field(I.lattice_instance((8, 4), 8), 0.6),
+    # average degree >= 16 (entry groups read ahead) with isolated vertices
+    # (slices without entries)
+    "er_dense_isolated": lambda: _with_isolated(I.er_instance(300, 11, p=0.12, weights="pm1"), 21),
 }
+
+
+def _with_isolated(inst, k):
+    """The instance with k isolated vertices appended (no couplings)."""
+    rowptr = np.concatenate([inst.rowptr, np.full(k, inst.rowptr[-1], dtype=np.int32)])
+    return I.CsrInstance(N=inst.N + k, rowptr=rowptr.astype(np.int32), col=inst.col, val=inst.val)
 
 
 def _with_field(inst, scale):
@@ -82,7 +91,8 @@ def test_damped_parity(case, update):
     assert err <= 1e-5, err
 
 
-RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "ea3d_8", "ea3d_16", "ea2d_6x4", "lat_field"]
+RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "er_dense_isolated", "ea3d_8", "ea3d_16", "ea2d_6x4",
+                   "lat_field"]
 
 
 @pytest.mark.parametrize("case", RUN_BLOCK_CASES)
