@@ -157,6 +157,32 @@ def copy_calibration():
                       "GB/s": 2 * n * 4 / ms / 1e6}), flush=True)
 
 
+def work_roofline(done, requests, makespan_s):
+    """The capacity pass against the roofline of its own work mix: every
+    completed request's algorithmic flops (2 per coupling term and update:
+    2N per spin-update for dense J, 2 nnz / N for sparse J) at the peak of
+    the unit that bounds its kernel (bf16 MFMA for dense requests, the fp32
+    vector ALU for sparse ones), summed into the time a perfectly fed GPU
+    would take; frac = that time / the measured makespan."""
+    by = {r.rid: r for r in requests}
+    flops = {"dense": 0.0, "sparse": 0.0}
+    ideal = 0.0
+    for c in done:
+        r = by[c.rid]
+        upd = float(c.result["spin_updates"])
+        if r.dense:
+            f = 2.0 * r.N * upd
+            ideal += f / (PEAK["bf16_mfma"] * 1e12)
+            flops["dense"] += f
+        else:
+            f = 2.0 * r.instance.nnz / r.N * upd
+            ideal += f / (PEAK["fp32_valu"] * 1e12)
+            flops["sparse"] += f
+    return {"dense_flop": flops["dense"], "sparse_flop": flops["sparse"], "dense_peak_tflops": PEAK["bf16_mfma"],
+            "sparse_peak_tflops": PEAK["fp32_valu"], "ideal_s": ideal, "makespan_s": makespan_s,
+            "frac": ideal / makespan_s if makespan_s > 0 else None}
+
+
 def served(args):
     """Served mixed stream: a capacity pass (all requests at t = 0), then
     Poisson passes at the given fractions of that capacity (default 0.7);
@@ -192,7 +218,8 @@ def served(args):
     warm = S.mixed_stream(4, 1e9, seed=args.seed + 7, n_hi=500)
     server.run(warm)
     log("capacity pass: %d requests" % len(base))
-    _, cap = server.run(base, progress=log)
+    done, cap = server.run(base, progress=log)
+    cap["work_roofline"] = work_roofline(done, base, cap["makespan_s"])
     capacity = cap["requests"] / cap["makespan_s"]
     log("capacity", cap, "-> %.2f req/s" % capacity)
     sweep = []
@@ -268,11 +295,15 @@ def main():
         forms = ["fp32", "bf16"]  # the exact-arithmetic form and the bf16 matrix-core form
     elif isinstance(w.instance, I.CsrInstance) and w.schedule.precision == "fp32":
         forms = ["fp32", "fp16"]  # fp32 state, and fp16 state storage with fp32 fields (twice the runs per CU)
+    elif isinstance(w.instance, I.LatticeInstance) and w.schedule.precision == "fp64":
+        forms = ["fp64", "fp32"]  # the fp64 form the oracle is compared with, and fp32 state
     else:
         forms = [w.schedule.precision]
 
-    def measure(prec):
+    def measure(prec, update=None):
         sch = w.schedule.replace(precision=prec)
+        if update is not None:
+            sch = sch.replace(update=update)
 
         def solve(sc):
             return inst.solve_ex(R, sc, args.seed, want_best=True, sync=False, stream=stream)
@@ -293,7 +324,8 @@ def main():
         wall = time.perf_counter() - t0
         step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
         ms = float(np.mean(step_ms))
-        log("%s: timed %d steps: %.3f ms/step (wall %.3f s)" % (prec, args.steps, ms, wall))
+        log("%s%s: timed %d steps: %.3f ms/step (wall %.3f s)"
+            % (prec, "" if update is None else " " + update, args.steps, ms, wall))
         # the same solve once more with host results: update count and summary
         once = inst.solve_ex(R, sch, args.seed, want_best=True, want_spins=True, sync=True, stream=stream)
         res = once["result"]
@@ -361,6 +393,19 @@ def main():
                      "equal_gap": p in eligible, "tts99_ms": tts99(measured[p], E_ref + tol, R),
                      "roofline": measured[p]["roofline"]} for p in forms}
     w.schedule = w.schedule.replace(precision=head)
+    # literal reading of the pseudocode (one synchronous phase) on the 2D
+    # lattice, timed like the forms: a fidelity row, never the headline (its
+    # runs fall into the 2-cycles of the synchronous update)
+    fidelity = None
+    if args.workload == "ea2d_L16" and not args.precision:
+        jm = measure("fp64", update="jacobi")
+        jr = jm["result"]
+        fidelity = {"jacobi_fp64": {"value": jm["value"], "ms_per_step": jm["ms_per_step"],
+                                    "best_energy": jr["best_energy"],
+                                    "best_energy_per_spin": jr["best_energy"] / N,
+                                    "mean_energy_per_spin": jr["mean_energy"] / N,
+                                    "positive_energy_runs": float(np.mean(jm["energies"] > 0))}}
+        del jm
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -382,6 +427,7 @@ def main():
                    "levels": w.schedule.steps, "parallelism": "single GPU, runs batched"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
         "forms": forms_out,
+        **({"fidelity": fidelity} if fidelity else {}),
         "result": {"best_energy": res["best_energy"], "best_energy_per_spin": res["best_energy"] / N,
                    "mean_energy_per_spin": res["mean_energy"] / N, "hit_count": res["hit_count"]},
         "roofline": roofline, "cpu_baseline": cpu,
