@@ -80,6 +80,7 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     a.L1 = I.L[1];
     a.L2 = I.dim == 3 ? I.L[2] : 1;
     a.bondbits = I.bondbits;
+    a.bondsgn = I.bondsgn;
     if (lat) {
         a.hhalf32 = I.has_h ? I.hhalf : nullptr;
         a.hhalf64 = I.has_h ? I.hhalf64 : nullptr;

@@ -27,6 +27,27 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x)
     __asm__ volatile("" : "+v"(x));
     return x;
 }
+__device__ __forceinline__ float opaque(float x)
+{
+    __asm__ volatile("" : "+v"(x));
+    return x;
+}
+// the same for a value that is uniform across the workgroup (kept in a
+// scalar register)
+__device__ __forceinline__ uint32_t opaque_uniform(uint32_t x)
+{
+    __asm__ volatile("" : "+s"(x));
+    return x;
+}
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+// two floats rounded to the nearest halves, packed low / high
+__device__ __forceinline__ uint32_t pack_halves(float lo, float hi)
+{
+    const half2_t h = __builtin_convertvector((float2_t){lo, hi}, half2_t);
+    return __builtin_bit_cast(uint32_t, h);
+}
 
 template <typename S, int VEC, int DIM, bool JAC, bool TRACKD, bool HAS_H, bool DAMP>
 __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
@@ -95,6 +116,9 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
     const int drow = Tq / H;
     const int nrows = L1 * L2;
     const int dy = drow % L1, dz = drow / L1;
+    // the lanes of a wave share cz0 when no boundary between walk columns of
+    // different start planes falls inside a wave
+    const bool zuni = cols && (nq >= 64 || (H * L1) % (64 / nq) == 0);
     // x offsets by parity p of x: p = 0 has x + 1 inside the row, p = 1 has x - 1
     const uint32_t oxp0 = ob(1), oxm0 = ob(xh > 0 ? -1 : L0 - 1);
     const uint32_t oxp1 = ob(xh < H - 1 ? 1 : 1 - L0), oxm1 = ob(-1);
@@ -220,8 +244,101 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
             }
             lds_put<S, VEC>(reinterpret_cast<S *>(wb + vb), nw);
         };
+        // Column walk of a packed pair of fp16 runs on a 3D lattice with an
+        // even walk step, every run of the thread annealing, undamped and
+        // without convergence tracking: the common case of long anneals, cut
+        // to the fewest vector instructions per site.
+        //  * the six bond signs come as one word per site holding three pairs
+        //    of fp16 sign bits (bits 15 - j and 31 - j for the bonds of axis
+        //    j), so a pair of +-1.0 halves is one and-or (and a shift) and each
+        //    term is one mixed-precision fma of two halves (exact product, one
+        //    rounding: the value of converting and adding);
+        //  * one byte-offset register walks the column, kept opaque so that
+        //    each neighbour address is one addition;
+        //  * with a walk step of two planes the +z neighbour of one site is the
+        //    -z neighbour of the next, so its word is carried, not re-read;
+        //  * when a plane of one colour spans whole waves, z is the same on
+        //    every lane and the loop runs on scalar registers.
+        // The terms are summed in the order of the general site update
+        // (+x, -x, +y, -y, +z, -z), so both give the same bits.
+        auto pair_walk = [&](auto uni, int p) {
+          if constexpr (sizeof(S) == 2 && VEC == 2 && DIM == 3) {
+            constexpr bool UNI = decltype(uni)::value;
+            int z = cz0;
+            if constexpr (UNI)
+                z = __builtin_amdgcn_readfirstlane(z);
+            int v = L0 * (cy + L1 * z) + 2 * xh + p;
+            uint32_t vb = ob(v);
+            const int dv = kz * plane;
+            const uint32_t dvb = ob(dv);
+            const uint32_t xp = opaque(p ? oxp1 : oxp0), xm = opaque(p ? oxm1 : oxm0);
+            const uint32_t yp = opaque(cyp), ym = opaque(cym);
+            const uint32_t zp = ob(plane), zm = ob(-plane), zpw = ob(plane - vol), zmw = ob(vol - plane);
+            const bool carry = kz == 2;
+            const uint32_t *__restrict__ sg = a.bondsgn;
+            auto rd = [&](uint32_t o) -> uint32_t { return *reinterpret_cast<const uint32_t *>(mb + o); };
+            auto lo = [](uint32_t u) -> float {
+                return (float)__builtin_bit_cast(_Float16, (unsigned short)(u & 0xffffu));
+            };
+            auto hi = [](uint32_t u) -> float {
+                return (float)__builtin_bit_cast(_Float16, (unsigned short)(u >> 16));
+            };
+            const float nzero = __uint_as_float(opaque(0x80000000u));  // -0 + x == x, also for x = +-0
+            // the sign-pair constants in registers (one and-or per pair)
+            const uint32_t smask = opaque(0x80008000u), sone = opaque_uniform(0x3c003c00u);
+            uint32_t uzm = rd(vb + (z > 0 ? zm : zmw));
+            uint32_t w = sg[v];
+            for (; z < L2; z += kz) {
+                const uint32_t wn = sg[v + dv];  // the next site's signs (the table holds 2N words)
+                const uint32_t u0 = rd(vb + xp), u1 = rd(vb + xm), u2 = rd(vb + yp), u3 = rd(vb + ym);
+                const uint32_t u4 = rd(vb + (z + 1 < L2 ? zp : zpw));
+                const uint32_t u5 = carry ? uzm : rd(vb + (z > 0 ? zm : zmw));
+                const uint32_t sx = (w & smask) | sone;
+                const uint32_t sy = ((w << 1) & smask) | sone;
+                const uint32_t sz = ((w << 2) & smask) | sone;
+                float p0 = __builtin_fmaf(lo(u0), lo(sx), nzero);
+                float p1 = __builtin_fmaf(hi(u0), lo(sx), nzero);
+                p0 = __builtin_fmaf(lo(u1), hi(sx), p0);
+                p1 = __builtin_fmaf(hi(u1), hi(sx), p1);
+                p0 = __builtin_fmaf(lo(u2), lo(sy), p0);
+                p1 = __builtin_fmaf(hi(u2), lo(sy), p1);
+                p0 = __builtin_fmaf(lo(u3), hi(sy), p0);
+                p1 = __builtin_fmaf(hi(u3), hi(sy), p1);
+                p0 = __builtin_fmaf(lo(u4), lo(sz), p0);
+                p1 = __builtin_fmaf(hi(u4), lo(sz), p1);
+                p0 = __builtin_fmaf(lo(u5), hi(sz), p0);
+                p1 = __builtin_fmaf(hi(u5), hi(sz), p1);
+                if (HAS_H) {
+                    const float hh = a.hhalf32[v];
+                    p0 += hh;
+                    p1 += hh;
+                }
+                // rounded to halves after the fp32 tanh (kept whole, so the
+                // conversion stays one packed instruction)
+                *reinterpret_cast<uint32_t *>(wb + vb) =
+                    pack_halves(opaque(l_tanh_run(p0, scale[0])), opaque(l_tanh_run(p1, scale[1])));
+                uzm = u4;
+                w = wn;
+                v += dv;
+                vb = opaque(vb + dvb);
+            }
+          }
+        };
         auto sweep = [&](auto live) {
             for (int c = 0; c < (JAC ? 1 : 2); ++c) {
+                constexpr bool PAIR_WALK = sizeof(S) == 2 && VEC == 2 && DIM == 3 && !JAC &&
+                                           decltype(live)::value && !DAMP && !TRACKD;
+                if constexpr (PAIR_WALK) {
+                    if (cols && (kz & 1) == 0) {
+                        const int p = (c + cy + cz0) & 1;
+                        if (zuni)
+                            pair_walk(std::true_type{}, p);
+                        else
+                            pair_walk(std::false_type{}, p);
+                        __syncthreads();
+                        continue;
+                    }
+                }
                 if (cols && !JAC && (kz & 1) == 0) {
                     // even walk step: the thread's x parity is fixed for the whole
                     // walk, so its site, x and y offsets are constants; only the

@@ -90,6 +90,9 @@ struct Instance {
     int dim = 0;
     int L[3] = {1, 1, 1};
     uint8_t *bondbits = nullptr;  // [N]: bit 2a set if J(v, v+e_a) < 0, bit 2a+1 if J(v, v-e_a) < 0
+    // [2N] (the second half repeats the first): per site the bond signs as
+    // fp16 sign bits, bit 15 - a for J(v, v+e_a) < 0, bit 31 - a for J(v, v-e_a) < 0
+    uint32_t *bondsgn = nullptr;
     // runtime
     hipStream_t own_stream = nullptr;
     // the instance's workspace is reused by every solve: a solve on another
@@ -223,10 +226,11 @@ struct GraphArgs {
     const int32_t *sl_meta;
     const uint32_t *colsell;
     const int32_t *cls;
-    int long_rows;  // sparse: average degree >= 16, entry groups are read one ahead
+    int long_rows;  // sparse: average degree >= 16, entry groups are read two ahead
     // lattice
     int dim, L0, L1, L2;
     const uint8_t *bondbits;
+    const uint32_t *bondsgn;
     // field
     const float *hhalf32;
     const double *hhalf64;

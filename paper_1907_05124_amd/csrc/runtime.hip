@@ -89,7 +89,7 @@ static void destroy_instance(Instance *I)
     }
     void *ptrs[] = {I->J,      I->Jbf,     I->Jfix,    I->Jlimb,   I->hhalf, I->hhalf64,
                     I->hfix,   I->rowptr,  I->colval,  I->perm,    I->sl_meta, I->colsell,
-                    I->cls,    I->hperm,   I->hperm64, I->bondbits};
+                    I->cls,    I->hperm,   I->hperm64, I->bondbits, I->bondsgn};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -603,9 +603,27 @@ static mars_status create_lattice(int dim, const int32_t *L, const int8_t *bond,
         }
         bits[v] = b;
     }
+    // the same signs as fp16 sign-bit positions: axis a's pair at bits 15 - a
+    // and 31 - a, so that shifting left by a and masking 0x80008000 yields the
+    // pair; twice over, so that a site index plus one walk step stays inside
+    std::vector<uint32_t> sgn((size_t)2 * N, 0);
+    for (long long v = 0; v < N; ++v) {
+        uint32_t w = 0;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (bits[v] >> (2 * ax) & 1)
+                w |= 1u << (15 - ax);
+            if (bits[v] >> (2 * ax + 1) & 1)
+                w |= 1u << (31 - ax);
+        }
+        sgn[v] = sgn[v + N] = w;
+    }
     if ((st = dev_alloc(&I->bondbits, (size_t)N)) != MARS_OK)
         return st;
+    if ((st = dev_alloc(&I->bondsgn, (size_t)2 * N)) != MARS_OK)
+        return st;
     MARS_HIP(hipMemcpyAsync(I->bondbits, bits.data(), (size_t)N, hipMemcpyHostToDevice, I->own_stream));
+    MARS_HIP(hipMemcpyAsync(I->bondsgn, sgn.data(), (size_t)2 * N * sizeof(uint32_t), hipMemcpyHostToDevice,
+                            I->own_stream));
     MARS_HIP(hipStreamSynchronize(I->own_stream));
     return upload_h(I, h, (int)N);
 }

@@ -37,6 +37,7 @@ CASES = {
     # 20x20x8: the walk step is odd, so the x parity alternates along it
     "ea3d_16": lambda: I.lattice_instance((16, 16, 16), 9),
     "ea3d_20x20x8": lambda: I.lattice_instance((20, 20, 8), 10),
+    "lat3d_field": lambda: _with_field(I.lattice_instance((16, 16, 16), 14), 0.6),
     "er_pm1": lambda: I.er_instance(800, 5, p=0.06, weights="pm1"),
     "er_unit": lambda: I.er_instance(300, 6, p=0.05, weights="unit"),
     "er_field": lambda: _with_field(I.er_instance(200, 7, p=0.05, weights="pm1"), 0.4),
@@ -165,8 +166,9 @@ def _dense_couplings(inst):
     return I.csr_dense(inst).J.astype(np.float64)
 
 
-@pytest.mark.parametrize("case", ["er_pm1", "er_field", "ea3d_8", "lat_field"])
-@pytest.mark.parametrize("R", [200, 1031, 4100])
+@pytest.mark.parametrize("case", ["er_pm1", "er_field", "ea3d_8", "lat_field", "ea3d_16", "ea3d_20x20x8",
+                                  "lat3d_field"])
+@pytest.mark.parametrize("R", [200, 1031, 2048, 4100])
 def test_one_level_fp16_storage(case, R):
     """fp16 magnetisation storage, fp32 fields, one level from fp16-exact
     initial states (the same for the oracle).  A spin's new value differs from
@@ -174,7 +176,13 @@ def test_one_level_fp16_storage(case, R):
     arithmetic, and by what it inherits from the phases before its own: a
     neighbour off by e_j moves Phi_i by |J_ij| e_j and m_i by at most
     (1 - m_i^2) / T times that (first order, with 10 % slack); the bound is
-    accumulated phase by phase."""
+    accumulated phase by phase.
+
+    On the 3D lattices, run pairs (R >= 1031) walk z columns with an even
+    step: 8^3 and 16^3 at R = 1031 four or eight planes apart, 16^3 at
+    R = 2048 and 20x20x8 at R = 1031 two planes apart (the +z word of one
+    site is carried as the -z word of the next; 20x20 planes do not split
+    into whole waves, so z differs between the lanes of a wave)."""
     M = _mars()
     torch = require_gpu()
     inst = CASES[case]()
