@@ -67,6 +67,27 @@ inline RunSchedule make_run_schedule(const mars_schedule &sc)
     return r;
 }
 
+// keeps a value opaque to the optimiser (no instruction is emitted): byte
+// offsets stay plain additions instead of being re-derived at every use, and
+// a load address is not related to the addresses of other iterations
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    __asm__ volatile("" : "+v"(x));
+    return x;
+}
+__device__ __forceinline__ float opaque(float x)
+{
+    __asm__ volatile("" : "+v"(x));
+    return x;
+}
+// the same for a value that is uniform across the workgroup (kept in a
+// scalar register)
+__device__ __forceinline__ uint32_t opaque_uniform(uint32_t x)
+{
+    __asm__ volatile("" : "+s"(x));
+    return x;
+}
+
 struct LevelWalker {
     double T0, lr, T;
     int k;      // level index in the run's schedule

@@ -20,26 +20,6 @@
 
 namespace mars {
 
-// keeps a value opaque to the optimiser, so that byte offsets stay plain
-// additions instead of being re-derived from site indices at every use
-__device__ __forceinline__ uint32_t opaque(uint32_t x)
-{
-    __asm__ volatile("" : "+v"(x));
-    return x;
-}
-__device__ __forceinline__ float opaque(float x)
-{
-    __asm__ volatile("" : "+v"(x));
-    return x;
-}
-// the same for a value that is uniform across the workgroup (kept in a
-// scalar register)
-__device__ __forceinline__ uint32_t opaque_uniform(uint32_t x)
-{
-    __asm__ volatile("" : "+s"(x));
-    return x;
-}
-
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef float float2_t __attribute__((ext_vector_type(2)));
 // two floats rounded to the nearest halves, packed low / high

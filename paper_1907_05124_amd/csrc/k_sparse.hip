@@ -129,55 +129,44 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                     const int off = rc.x;
                     const int w = rc.y;
                     rc = rn;
-                    const uint32_t *cp = colsell + off + ((unsigned)slot % SELL_H);
+                    // the slot's entry groups: 16 contiguous bytes each, one
+                    // slice (SELL_H slots) apart
+                    const uint4 *gp = reinterpret_cast<const uint4 *>(colsell + off) + ((unsigned)slot % SELL_H);
                     C phi[VEC];
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
                         phi[e] = 0;
                     // w is a multiple of SELL_W: whole groups, no remainder loop
-                    auto group = [&](const uint32_t *cb) {
+                    auto group = [&](const uint4 cb) {
+                        const uint32_t ent[SELL_W] = {cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
                         for (int u = 0; u < SELL_W; ++u) {
-                            const C wt = entry_weight<C, UNIT>(cb[u]);
+                            const C wt = entry_weight<C, UNIT>(ent[u]);
                             const Pack<S, VEC> t =
-                                lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((cb[u] & 0xffffffu) << lgs)));
+                                lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((ent[u] & 0xffffffu) << lgs)));
 #pragma unroll
                             for (int e = 0; e < VEC; ++e)
                                 phi[e] += wt * LStore<S>::ld(t.v[e]);
                         }
                     };
                     if (!long_rows) {
-                        for (int j = 0; j < w; j += SELL_W) {
-                            uint32_t cb[SELL_W];
-#pragma unroll
-                            for (int u = 0; u < SELL_W; ++u)
-                                cb[u] = cp[(j + u) * SELL_H];
-                            group(cb);
-                        }
+                        for (int j = 0, g = 0; j < w; j += SELL_W, ++g)
+                            group(gp[g * SELL_H]);
                     } else if (w > 0) {
                         // long rows (high average degree): entry groups are
-                        // read two groups ahead of the one being summed (past
-                        // the row's end the last group is re-read: in bounds,
-                        // unused; a slice without entries reads nothing)
-                        const int wl = w - SELL_W;  // start of the last group
-                        uint32_t cb[SELL_W], n1[SELL_W];
-#pragma unroll
-                        for (int u = 0; u < SELL_W; ++u) {
-                            cb[u] = cp[u * SELL_H];
-                            n1[u] = cp[(min(SELL_W, wl) + u) * SELL_H];
-                        }
-                        for (int j = 0; j < w; j += SELL_W) {
-                            const int j2 = min(j + 2 * SELL_W, wl);
-                            uint32_t n2[SELL_W];
-#pragma unroll
-                            for (int u = 0; u < SELL_W; ++u)
-                                n2[u] = cp[(j2 + u) * SELL_H];
+                        // read ahead of the one being summed; reads run up to
+                        // two groups past the slice, into the next slice or
+                        // the table's padding (in bounds, unused), and a slice
+                        // without entries reads nothing
+                        uint4 cb = gp[0], n1 = gp[SELL_H];
+                        for (int j = 0, g = 2; j < w; j += SELL_W, ++g) {
+                            // (an opaque index keeps the read ahead: otherwise
+                            // it is turned back into a read of the current
+                            // group at its use)
+                            const uint4 n2 = gp[opaque((uint32_t)g * SELL_H)];
                             group(cb);
-#pragma unroll
-                            for (int u = 0; u < SELL_W; ++u) {
-                                cb[u] = n1[u];
-                                n1[u] = n2[u];
-                            }
+                            cb = n1;
+                            n1 = n2;
                         }
                     }
                     if (HAS_H) {

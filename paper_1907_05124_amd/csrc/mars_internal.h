@@ -74,9 +74,12 @@ struct Instance {
     // and padded to a multiple of SELL_H slots; slice s (SELL_H consecutive
     // slots) holds width w_s = its largest degree rounded up to a multiple
     // of SELL_W and entries
-    // colsell[off_s + j * SELL_H + (slot % SELL_H)], j < w_s, each
+    // colsell[off_s + ((j / SELL_W) * SELL_H + slot % SELL_H) * SELL_W + j % SELL_W],
+    // j < w_s (a slot's group of SELL_W entries is 16 contiguous bytes, and
+    // the SELL_H slots of a slice read 128 contiguous bytes per group), each
     // (neighbour slot) | (uint8(weight) << 24); a missing entry names the
-    // all-zero row nslot with weight +1
+    // all-zero row nslot with weight +1; two groups of such entries
+    // (2 x SELL_W x SELL_H) follow the last slice
     int nslot = 0;
     bool unit = false;            // every |weight| == 1
     int32_t *perm = nullptr;      // [nslot] slot -> vertex, -1 for padding
@@ -226,7 +229,7 @@ struct GraphArgs {
     const int32_t *sl_meta;
     const uint32_t *colsell;
     const int32_t *cls;
-    int long_rows;  // sparse: average degree >= 16, entry groups are read two ahead
+    int long_rows;  // sparse: average degree >= 16, entry groups are read ahead
     // lattice
     int dim, L0, L1, L2;
     const uint8_t *bondbits;

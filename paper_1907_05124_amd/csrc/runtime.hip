@@ -489,7 +489,9 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
     }
     if (total >= (size_t)1 << 31)
         return set_error(MARS_E_UNSUPPORTED, "sliced layout exceeds 2^31 entries");
-    std::vector<uint32_t> cs(std::max<size_t>(total, 1), (uint32_t)nslot | (1u << 24));
+    // two entry groups of padding after the last slice: the solver reads
+    // that far ahead of the group it sums
+    std::vector<uint32_t> cs(total + (size_t)2 * SELL_W * SELL_H, (uint32_t)nslot | (1u << 24));
     bool unit = true;
     for (int sl = 0; sl < nslice; ++sl)
         for (int l = 0; l < SELL_H; ++l) {
@@ -497,7 +499,8 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
             if (v < 0)
                 continue;
             for (int k = rowptr[v]; k < rowptr[v + 1]; ++k) {
-                const size_t at = (size_t)meta[2 * sl] + (size_t)(k - rowptr[v]) * SELL_H + l;
+                const int j = k - rowptr[v];
+                const size_t at = (size_t)meta[2 * sl] + ((size_t)(j / SELL_W) * SELL_H + l) * SELL_W + j % SELL_W;
                 cs[at] = (uint32_t)slot_of[col[k]] | ((uint32_t)(uint8_t)val[k] << 24);
                 unit &= (val[k] == 1 || val[k] == -1);
             }
