@@ -30,8 +30,8 @@ namespace mars {
 template <typename C, bool UNIT>
 __device__ inline C entry_weight(uint32_t cb)
 {
-    if constexpr (UNIT && sizeof(C) == 4)
-        return __uint_as_float((cb & 0x80000000u) | 0x3f800000u);
+    if constexpr (UNIT)
+        return (C)__uint_as_float((cb & 0x80000000u) | 0x3f800000u);
     else
         return (C)((int32_t)cb >> 24);
 }
@@ -136,14 +136,18 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
                         phi[e] = 0;
-                    // w is a multiple of SELL_W: whole groups, no remainder loop
+                    // w is a multiple of SELL_W: whole groups, no remainder loop.
+                    // A +-1 entry holds only its sign above the slot (bit 31,
+                    // shifted out with the byte offset: lgs >= 1), an int8
+                    // entry its weight byte in bits 24-31
+                    constexpr uint32_t colmask = UNIT ? 0xffffffffu : 0xffffffu;
                     auto group = [&](const uint4 cb) {
                         const uint32_t ent[SELL_W] = {cb.x, cb.y, cb.z, cb.w};
 #pragma unroll
                         for (int u = 0; u < SELL_W; ++u) {
                             const C wt = entry_weight<C, UNIT>(ent[u]);
                             const Pack<S, VEC> t =
-                                lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((ent[u] & 0xffffffu) << lgs)));
+                                lds_get<S, VEC>(reinterpret_cast<const S *>(mb + ((ent[u] & colmask) << lgs)));
 #pragma unroll
                             for (int e = 0; e < VEC; ++e)
                                 phi[e] += wt * LStore<S>::ld(t.v[e]);

@@ -77,9 +77,10 @@ struct Instance {
     // colsell[off_s + ((j / SELL_W) * SELL_H + slot % SELL_H) * SELL_W + j % SELL_W],
     // j < w_s (a slot's group of SELL_W entries is 16 contiguous bytes, and
     // the SELL_H slots of a slice read 128 contiguous bytes per group), each
-    // (neighbour slot) | (uint8(weight) << 24); a missing entry names the
-    // all-zero row nslot with weight +1; two groups of such entries
-    // (2 x SELL_W x SELL_H) follow the last slice
+    // (neighbour slot) | (uint8(weight) << 24), or, when every weight is
+    // +-1 (unit), (neighbour slot) | (weight < 0) << 31; a missing entry
+    // names the all-zero row nslot with weight +1; two groups of such
+    // entries (2 x SELL_W x SELL_H) follow the last slice
     int nslot = 0;
     bool unit = false;            // every |weight| == 1
     int32_t *perm = nullptr;      // [nslot] slot -> vertex, -1 for padding

@@ -489,10 +489,14 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
     }
     if (total >= (size_t)1 << 31)
         return set_error(MARS_E_UNSUPPORTED, "sliced layout exceeds 2^31 entries");
+    // +-1 weights keep only the sign, in bit 31 (the solver then shifts the
+    // entry into a byte offset without masking); other weights the int8 byte
+    bool unit = true;
+    for (long long k = 0; k < (long long)rowptr[N]; ++k)
+        unit &= (val[k] == 1 || val[k] == -1);
     // two entry groups of padding after the last slice: the solver reads
     // that far ahead of the group it sums
-    std::vector<uint32_t> cs(total + (size_t)2 * SELL_W * SELL_H, (uint32_t)nslot | (1u << 24));
-    bool unit = true;
+    std::vector<uint32_t> cs(total + (size_t)2 * SELL_W * SELL_H, unit ? (uint32_t)nslot : (uint32_t)nslot | (1u << 24));
     for (int sl = 0; sl < nslice; ++sl)
         for (int l = 0; l < SELL_H; ++l) {
             const int v = perm[(size_t)sl * SELL_H + l];
@@ -501,8 +505,8 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
             for (int k = rowptr[v]; k < rowptr[v + 1]; ++k) {
                 const int j = k - rowptr[v];
                 const size_t at = (size_t)meta[2 * sl] + ((size_t)(j / SELL_W) * SELL_H + l) * SELL_W + j % SELL_W;
-                cs[at] = (uint32_t)slot_of[col[k]] | ((uint32_t)(uint8_t)val[k] << 24);
-                unit &= (val[k] == 1 || val[k] == -1);
+                cs[at] = (uint32_t)slot_of[col[k]] |
+                         (unit ? (val[k] < 0 ? 0x80000000u : 0u) : ((uint32_t)(uint8_t)val[k] << 24));
             }
         }
     I->nslot = nslot;

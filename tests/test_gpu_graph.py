@@ -45,7 +45,21 @@ CASES = {
     # average degree >= 16 (entry groups read ahead) with isolated vertices
     # (slices without entries)
     "er_dense_isolated": lambda: _with_isolated(I.er_instance(300, 11, p=0.12, weights="pm1"), 21),
+    # int8 weights other than +-1 (the general entry encoding), short and long rows
+    "er_int8": lambda: _with_int8_weights(I.er_instance(500, 15, p=0.01, weights="pm1")),
+    "er_int8_dense": lambda: _with_int8_weights(I.er_instance(300, 16, p=0.1, weights="pm1")),
 }
+
+
+def _with_int8_weights(inst):
+    """The instance with nonzero weights in -3..3: the sign of the original
+    weight times 1 + ((31 min(i, j) + 17 max(i, j)) mod 3), equal for both
+    directions of an edge."""
+    rows = np.repeat(np.arange(inst.N), np.diff(inst.rowptr))
+    lo, hi = np.minimum(rows, inst.col), np.maximum(rows, inst.col)
+    mag = 1 + (31 * lo.astype(np.int64) + 17 * hi.astype(np.int64)) % 3
+    return I.CsrInstance(N=inst.N, rowptr=inst.rowptr, col=inst.col,
+                         val=(np.sign(inst.val) * mag).astype(np.int8))
 
 
 def _with_isolated(inst, k):
@@ -92,8 +106,8 @@ def test_damped_parity(case, update):
     assert err <= 1e-5, err
 
 
-RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "er_dense_isolated", "ea3d_8", "ea3d_16", "ea2d_6x4",
-                   "lat_field"]
+RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "er_dense_isolated", "er_int8", "er_int8_dense", "ea3d_8",
+                   "ea3d_16", "ea2d_6x4", "lat_field"]
 
 
 @pytest.mark.parametrize("case", RUN_BLOCK_CASES)
@@ -166,8 +180,8 @@ def _dense_couplings(inst):
     return I.csr_dense(inst).J.astype(np.float64)
 
 
-@pytest.mark.parametrize("case", ["er_pm1", "er_field", "ea3d_8", "lat_field", "ea3d_16", "ea3d_20x20x8",
-                                  "lat3d_field"])
+@pytest.mark.parametrize("case", ["er_pm1", "er_field", "er_int8_dense", "ea3d_8", "lat_field", "ea3d_16",
+                                  "ea3d_20x20x8", "lat3d_field"])
 @pytest.mark.parametrize("R", [200, 1031, 2048, 4100])
 def test_one_level_fp16_storage(case, R):
     """fp16 magnetisation storage, fp32 fields, one level from fp16-exact
