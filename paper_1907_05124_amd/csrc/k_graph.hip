@@ -89,6 +89,15 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
         a.hhalf64 = I.has_h ? I.hperm64 : nullptr;
     }
     a.rs = make_run_schedule(sc);
+    // geometric schedules: the levels from first to the walker's stop, the
+    // length of the block's level table (kept by the launcher if it fits)
+    a.ttab = 0;
+    if (a.rs.kind == MARS_GEOMETRIC) {
+        int stop = a.rs.steps;
+        if (a.rs.count >= 0 && a.rs.first + a.rs.count < stop)
+            stop = a.rs.first + a.rs.count;
+        a.ttab = std::max(0, stop - a.rs.first);
+    }
     a.max_sweeps = sc.max_sweeps;
     a.d_min = sc.d_min;
     a.damping = sc.damping;

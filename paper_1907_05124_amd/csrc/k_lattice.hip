@@ -72,6 +72,21 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
         rsl[q].start(a.rs, r < a.R ? a.T0[r] : 1.0, r < a.R);
         dq[q] = 0;
     }
+    // geometric schedules: every level's T and 1/T of the block's runs,
+    // computed side by side once, so that a level advance is a table read
+    const int ttab = a.ttab;
+    const size_t tab_off = (state_bytes + (size_t)rpw * RUN_AREA_BYTES + 7) & ~(size_t)7;
+    double *tT = reinterpret_cast<double *>(smem_raw + tab_off);
+    float *tI = reinterpret_cast<float *>(tT + (size_t)rpw * ttab);
+    if (ttab) {
+        __syncthreads();  // the runs' level walkers are set
+        for (int i = threadIdx.x; i < rpw * ttab; i += blockDim.x) {
+            const int q = i / ttab;
+            const double T = rsl[q].lw.geometric_T(a.rs, a.rs.first + (i - q * ttab));
+            tT[i] = T;
+            tI[i] = (float)(1.0 / T);
+        }
+    }
     const C g = (C)a.damping;
 
     const int L0 = a.L0, L1 = a.L1, L2 = a.L2;
@@ -394,12 +409,12 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
                     atomicMax(&dq[q0 + e], __float_as_uint((float)dloc[e]));
             __syncthreads();
         }
-        if (tq == 0) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                rsl[q0 + e].end_sweep(a.rs, __uint_as_float(dq[q0 + e]), TRACKD, a.max_sweeps, a.d_min);
-                dq[q0 + e] = 0;
-            }
+        // each run's level advance (an fp64 exp and divide on geometric
+        // schedules) on its own lane of the first wave, side by side
+        for (int q = threadIdx.x; q < rpw; q += blockDim.x) {
+            rsl[q].end_sweep(a.rs, __uint_as_float(dq[q]), TRACKD, a.max_sweeps, a.d_min,
+                             ttab ? tT + (size_t)q * ttab : nullptr, ttab ? tI + (size_t)q * ttab : nullptr);
+            dq[q] = 0;
         }
         __syncthreads();
     }
@@ -471,7 +486,7 @@ hipError_t launch_lattice_solve(const GraphArgs &a, int esz, int rpw, bool jac, 
     const int H = a.L0 / 2;
     const int N = a.N;
     const size_t per_run = (size_t)N * esz * (jac ? 2 : 1);
-    const size_t lds = (((size_t)rpw * per_run + 15) & ~(size_t)15) + rpw * RUN_AREA_BYTES;
+    const size_t base_lds = (((size_t)rpw * per_run + 15) & ~(size_t)15) + rpw * RUN_AREA_BYTES;
     // threads per run group, at most 1024 per workgroup: whole planes of one
     // colour (H x L1 sites) when one fits, so that threads walk columns along
     // z; otherwise a multiple of the half-row length H, no more than one per
@@ -487,13 +502,16 @@ hipError_t launch_lattice_solve(const GraphArgs &a, int esz, int rpw, bool jac, 
     if (Tq * nq > 1024)
         return hipErrorInvalidConfiguration;
     dim3 grid((a.R + rpw - 1) / rpw), block(Tq * nq);
+    GraphArgs b = a;
+    b.ttab = level_table_fit(a.ttab, rpw, base_lds, Tq * nq, grid.x);
+    const size_t lds = base_lds + level_table_bytes(rpw, b.ttab);
     if (esz == 8)
-        return lat_launch<double, 1>(a, lg, jac, trackd, grid, block, lds, s);
+        return lat_launch<double, 1>(b, lg, jac, trackd, grid, block, lds, s);
     if (esz == 4)
-        return vec == 2 ? lat_launch<float, 2>(a, lg, jac, trackd, grid, block, lds, s)
-                        : lat_launch<float, 1>(a, lg, jac, trackd, grid, block, lds, s);
-    return vec == 2 ? lat_launch<_Float16, 2>(a, lg, jac, trackd, grid, block, lds, s)
-                    : lat_launch<_Float16, 1>(a, lg, jac, trackd, grid, block, lds, s);
+        return vec == 2 ? lat_launch<float, 2>(b, lg, jac, trackd, grid, block, lds, s)
+                        : lat_launch<float, 1>(b, lg, jac, trackd, grid, block, lds, s);
+    return vec == 2 ? lat_launch<_Float16, 2>(b, lg, jac, trackd, grid, block, lds, s)
+                    : lat_launch<_Float16, 1>(b, lg, jac, trackd, grid, block, lds, s);
 }
 
 }  // namespace mars

@@ -80,6 +80,21 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
         rsl[q].start(a.rs, r < a.R ? a.T0[r] : 1.0, r < a.R);
         dq[q] = 0;
     }
+    // geometric schedules: every level's T and 1/T of the block's runs,
+    // computed side by side once, so that a level advance is a table read
+    const int ttab = a.ttab;
+    const size_t tab_off = (state_bytes + (size_t)rpw * RUN_AREA_BYTES + 7) & ~(size_t)7;
+    double *tT = reinterpret_cast<double *>(smem_raw + tab_off);
+    float *tI = reinterpret_cast<float *>(tT + (size_t)rpw * ttab);
+    if (ttab) {
+        __syncthreads();  // the runs' level walkers are set
+        for (int i = threadIdx.x; i < rpw * ttab; i += blockDim.x) {
+            const int q = i / ttab;
+            const double T = rsl[q].lw.geometric_T(a.rs, a.rs.first + (i - q * ttab));
+            tT[i] = T;
+            tI[i] = (float)(1.0 / T);
+        }
+    }
     const C g = (C)a.damping;
     int lgs = lg_rpw;  // log2 of the byte stride of one slot's row
     for (int sz = (int)sizeof(S); sz > 1; sz >>= 1)
@@ -226,12 +241,12 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                     atomicMax(&dq[q0 + e], __float_as_uint((float)dloc[e]));
             __syncthreads();
         }
-        if (tq == 0) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-                rsl[q0 + e].end_sweep(a.rs, __uint_as_float(dq[q0 + e]), TRACKD, a.max_sweeps, a.d_min);
-                dq[q0 + e] = 0;
-            }
+        // each run's level advance (an fp64 exp and divide on geometric
+        // schedules) on its own lane of the first wave, side by side
+        for (int q = threadIdx.x; q < rpw; q += blockDim.x) {
+            rsl[q].end_sweep(a.rs, __uint_as_float(dq[q]), TRACKD, a.max_sweeps, a.d_min,
+                             ttab ? tT + (size_t)q * ttab : nullptr, ttab ? tI + (size_t)q * ttab : nullptr);
+            dq[q] = 0;
         }
         __syncthreads();
     }
@@ -308,10 +323,13 @@ hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int
              : vec == 2 ? sp_pick_d<_Float16, 2>(damp, has_h, unit, jac, trackd)
                         : sp_pick_d<_Float16, 1>(damp, has_h, unit, jac, trackd);
     const size_t rows = (size_t)a.nslot + 1;
-    const size_t lds = ((rows * rpw * esz * (jac ? 2 : 1) + 15) & ~(size_t)15) + rpw * RUN_AREA_BYTES;
+    const size_t base_lds = ((rows * rpw * esz * (jac ? 2 : 1) + 15) & ~(size_t)15) + rpw * RUN_AREA_BYTES;
     const int nq = rpw / (esz == 8 ? 1 : vec);
     if (Tq * nq > 1024 || Tq < 1)
         return hipErrorInvalidConfiguration;
+    GraphArgs b = a;
+    b.ttab = level_table_fit(a.ttab, rpw, base_lds, Tq * nq, (a.R + rpw - 1) / rpw);
+    const size_t lds = base_lds + level_table_bytes(rpw, b.ttab);
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -319,7 +337,7 @@ hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int
             return e;
     }
     dim3 grid((a.R + rpw - 1) / rpw), block(Tq * nq);
-    hipLaunchKernelGGL(fn, grid, block, lds, s, a, lg);
+    hipLaunchKernelGGL(fn, grid, block, lds, s, b, lg);
     return hipGetLastError();
 }
 

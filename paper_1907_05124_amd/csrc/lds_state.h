@@ -128,10 +128,23 @@ struct RunState {
         invT32 = done ? 0.0f : (float)(1.0 / lw.T);
         sw = sweeps = levels = caps = 0;
     }
-    __device__ void advance(const RunSchedule &rs)
+    // tT / tI: the run's row of the block's level table (geometric schedules,
+    // filled from the same walker before the first sweep), or null
+    __device__ void advance(const RunSchedule &rs, const double *tT, const float *tI)
     {
         ++levels;
         sw = 0;
+        if (tT) {
+            ++lw.k;
+            if (lw.k >= lw.stop) {
+                lw.done = true;
+                done = 1;
+                return;
+            }
+            lw.T = T = tT[lw.k - rs.first];
+            invT32 = tI[lw.k - rs.first];
+            return;
+        }
         lw.next(rs);
         if (lw.done) {
             done = 1;
@@ -142,13 +155,14 @@ struct RunState {
     }
     // d: the run's largest change in the sweep (fp32 image), read only when
     // several sweeps per level are allowed
-    __device__ void end_sweep(const RunSchedule &rs, float d, bool trackd, int max_sweeps, double d_min)
+    __device__ void end_sweep(const RunSchedule &rs, float d, bool trackd, int max_sweeps, double d_min,
+                              const double *tT, const float *tI)
     {
         if (done)
             return;
         ++sweeps;
         if (!trackd) {
-            advance(rs);
+            advance(rs, tT, tI);
             return;
         }
         ++sw;
@@ -156,7 +170,7 @@ struct RunState {
         if (conv || sw >= max_sweeps) {
             if (!conv && max_sweeps > 1)
                 ++caps;
-            advance(rs);
+            advance(rs, tT, tI);
         }
     }
     __device__ void write_stats(int64_t *runstat, int run) const

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -18,6 +19,30 @@ enum Kind { KIND_DENSE = 0, KIND_CSR = 1, KIND_LATTICE = 2 };
 constexpr int SELL_H = 8;  // slots per slice of the sparse solver's layout
 constexpr int SELL_W = 4;  // slice widths are padded to a multiple of this
 constexpr size_t RUN_AREA_MAX = 96;  // LDS bytes reserved per run for its level state
+// LDS level table of an LDS-resident solver's block (geometric schedules):
+// per run, T (fp64) then, for all runs, 1/T (fp32) of each level the run
+// visits, after the runs' level records (8-byte aligned)
+inline size_t level_table_bytes(int rpw, int ttab)
+{
+    return ttab > 0 ? 8 + (size_t)rpw * ttab * 12 : 0;
+}
+// the table of n levels is kept where it fits the LDS budget without
+// lowering the number of the launch's workgroups resident on a CU (160 KB of
+// LDS and 32 waves per CU, blocks spread over 256 CUs); 0: walk the levels
+inline int level_table_fit(int n, int rpw, size_t base_lds, int threads, long long blocks)
+{
+    if (n <= 0)
+        return 0;
+    const size_t with = base_lds + level_table_bytes(rpw, n);
+    if (with > 160 * 1024 - 1024)
+        return 0;
+    auto resident = [&](size_t bytes) {
+        long long r = (long long)((160 * 1024) / bytes);
+        r = std::min(r, (long long)(32 / ((threads + 63) / 64)));
+        return std::min(r, (blocks + 255) / 256);
+    };
+    return resident(with) >= resident(base_lds) ? n : 0;
+}
 
 // Device buffer owned by an instance; grows on demand, freed on destroy.
 struct DevBuf {
@@ -231,6 +256,7 @@ struct GraphArgs {
     const uint32_t *colsell;
     const int32_t *cls;
     int long_rows;  // sparse: average degree >= 16, entry groups are read ahead
+    int ttab;       // geometric schedules: levels in the block's LDS level table (0: none)
     // lattice
     int dim, L0, L1, L2;
     const uint8_t *bondbits;
