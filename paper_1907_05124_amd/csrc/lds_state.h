@@ -188,13 +188,15 @@ constexpr size_t RUN_AREA_BYTES = sizeof(RunState) + sizeof(uint32_t);
 static_assert(RUN_AREA_BYTES <= RUN_AREA_MAX, "per-run LDS area exceeds the launcher's reservation");
 
 // tanh(Phi / T) from a per-run factor ts (run_tscale): fp32 folds the
-// exp2 constant of l_tanh into the factor, ts = 2 log2(e) / T, saving a
-// multiply per update; fp64 divides by T and takes the libm tanh
+// exp2 constant into the factor, ts = 2 log2(e) / T, and takes
+// tanh(a) = 2 / (1 + exp(-2a)) - 1, which keeps the sign by itself (exp2 of
+// a large argument is +inf and its reciprocal 0, so the ends are exactly -1
+// and +1; absolute error ~1e-7 near 0, as for the form on |a|); fp64 divides
+// by T
 __device__ inline float l_tanh_run(float phi, float ts)
 {
-    const float e = __builtin_amdgcn_exp2f(fabsf(phi) * ts);
-    const float t = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
-    return copysignf(t, phi);
+    const float e = __builtin_amdgcn_exp2f(-phi * ts);
+    return __builtin_fmaf(2.0f, __builtin_amdgcn_rcpf(1.0f + e), -1.0f);
 }
 // fp64: tanh(a) = expm1(2|a|) / (expm1(2|a|) + 2) with the sign of a
 // (accurate near 0 through expm1; a few ulp), a third of the instructions
