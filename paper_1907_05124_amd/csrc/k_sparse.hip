@@ -80,8 +80,8 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
         rsl[q].start(a.rs, r < a.R ? a.T0[r] : 1.0, r < a.R);
         dq[q] = 0;
     }
-    // geometric schedules: every level's T and 1/T of the block's runs,
-    // computed side by side once, so that a level advance is a table read
+    // geometric schedules: every level's 1/T (fp64 and fp32) of the block's
+    // runs, computed side by side once, so that a level advance is a table read
     const int ttab = a.ttab;
     const size_t tab_off = (state_bytes + (size_t)rpw * RUN_AREA_BYTES + 7) & ~(size_t)7;
     double *tT = reinterpret_cast<double *>(smem_raw + tab_off);
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
         for (int i = threadIdx.x; i < rpw * ttab; i += blockDim.x) {
             const int q = i / ttab;
             const double T = rsl[q].lw.geometric_T(a.rs, a.rs.first + (i - q * ttab));
-            tT[i] = T;
+            tT[i] = 1.0 / T;
             tI[i] = (float)(1.0 / T);
         }
     }

@@ -114,7 +114,7 @@ __device__ inline void lds_put(S *p, const Pack<S, VEC> &r)
 // change d falls below d_min.  The other threads only read T, invT and done.
 struct RunState {
     LevelWalker lw;
-    double T;
+    double invT64;  // 1/T of the current level
     float invT32;
     int done;
     int sw;       // sweeps at the current level
@@ -124,12 +124,13 @@ struct RunState {
     {
         lw.start(rs, live ? T0 : 1.0);
         done = (!live || lw.done) ? 1 : 0;
-        T = done ? 1.0 : lw.T;
+        invT64 = done ? 1.0 : 1.0 / lw.T;
         invT32 = done ? 0.0f : (float)(1.0 / lw.T);
         sw = sweeps = levels = caps = 0;
     }
-    // tT / tI: the run's row of the block's level table (geometric schedules,
-    // filled from the same walker before the first sweep), or null
+    // tT / tI: the run's row of the block's level table of 1/T in fp64 and
+    // fp32 (geometric schedules, filled from the same walker before the first
+    // sweep), or null
     __device__ void advance(const RunSchedule &rs, const double *tT, const float *tI)
     {
         ++levels;
@@ -141,7 +142,7 @@ struct RunState {
                 done = 1;
                 return;
             }
-            lw.T = T = tT[lw.k - rs.first];
+            invT64 = tT[lw.k - rs.first];
             invT32 = tI[lw.k - rs.first];
             return;
         }
@@ -149,7 +150,7 @@ struct RunState {
         if (lw.done) {
             done = 1;
         } else {
-            T = lw.T;
+            invT64 = 1.0 / lw.T;
             invT32 = (float)(1.0 / lw.T);
         }
     }
@@ -198,12 +199,13 @@ __device__ inline float l_tanh_run(float phi, float ts)
     const float e = __builtin_amdgcn_exp2f(-phi * ts);
     return __builtin_fmaf(2.0f, __builtin_amdgcn_rcpf(1.0f + e), -1.0f);
 }
-// fp64: tanh(a) = expm1(2|a|) / (expm1(2|a|) + 2) with the sign of a
+// fp64: a = Phi * (1/T) (within an ulp of Phi / T, without a division per
+// update), tanh(a) = expm1(2|a|) / (expm1(2|a|) + 2) with the sign of a
 // (accurate near 0 through expm1; a few ulp), a third of the instructions
 // of the library tanh; |a| > 20 rounds to +-1 in double
-__device__ inline double l_tanh_run(double phi, double T)
+__device__ inline double l_tanh_run(double phi, double invT)
 {
-    const double a = phi / T;
+    const double a = phi * invT;
     const double x = fabs(a);
     const double e = expm1(2.0 * x);
     const double t = x > 20.0 ? 1.0 : e / (e + 2.0);
@@ -211,16 +213,10 @@ __device__ inline double l_tanh_run(double phi, double T)
 }
 
 template <typename C>
-__device__ inline C run_scale(const RunState &r);
-template <>
-__device__ inline float run_scale<float>(const RunState &r) { return r.invT32; }
-template <>
-__device__ inline double run_scale<double>(const RunState &r) { return r.T; }
-template <typename C>
 __device__ inline C run_tscale(const RunState &r);
 template <>
 __device__ inline float run_tscale<float>(const RunState &r) { return r.invT32 * 2.8853900817779268f; }
 template <>
-__device__ inline double run_tscale<double>(const RunState &r) { return r.T; }
+__device__ inline double run_tscale<double>(const RunState &r) { return r.invT64; }
 
 }  // namespace mars

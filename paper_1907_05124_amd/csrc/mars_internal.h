@@ -20,8 +20,8 @@ constexpr int SELL_H = 8;  // slots per slice of the sparse solver's layout
 constexpr int SELL_W = 4;  // slice widths are padded to a multiple of this
 constexpr size_t RUN_AREA_MAX = 96;  // LDS bytes reserved per run for its level state
 // LDS level table of an LDS-resident solver's block (geometric schedules):
-// per run, T (fp64) then, for all runs, 1/T (fp32) of each level the run
-// visits, after the runs' level records (8-byte aligned)
+// 1/T in fp64 for every run and level it visits, then the same in fp32,
+// after the runs' level records (8-byte aligned)
 inline size_t level_table_bytes(int rpw, int ttab)
 {
     return ttab > 0 ? 8 + (size_t)rpw * ttab * 12 : 0;
