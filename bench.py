@@ -27,16 +27,30 @@ METRIC = "spin-updates/s (runs×N×steps) at equal best-energy gap; p50/p99 solv
 # (the library is built without it): 256 CUs x 64 lanes x 2 flops x 2.4 GHz.
 PEAK = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0, "fp32_valu": 78.6, "fp64_valu": 78.6}
 
-# HBM bytes of one dense phase launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
-# (KiB per dispatch, SK2000 workload), scaled by the counters' reading of a
-# plain 256 MiB copy.  Valid only for the kernel source they were taken on.
+# HBM bytes of one launch of the dominant kernel from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE (KiB per dispatch), scaled by the counters' reading of a plain
+# 256 MiB copy, by (workload, form).  Valid only for the kernel source they
+# were taken on.  The LDS-resident solvers read almost nothing from HBM: what
+# they write is the rounded spins (one byte per spin and run) and run counters.
 TRAFFIC_RECORD = {
-    "fp32": {"source": "paper_1907_05124_amd/csrc/dense_phase.h", "sha256_prefix": "4be37f4594fd5dee",
-             "workload": "sk2000", "fetch_kib": 54899.4, "write_kib": 16000.0,
-             "fetch_scale": 2.0, "write_scale": 1.0, "summary": "profiles/k_dense_phase_f32_sk2000.md"},
-    "bf16": {"source": "paper_1907_05124_amd/csrc/dense_phase_bf16.h", "sha256_prefix": "237f59c1c1e9c87f",
-             "workload": "sk2000", "fetch_kib": 26428.9, "write_kib": 8256.0,
-             "fetch_scale": 2.0, "write_scale": 1.0, "summary": "profiles/k_dense_phase_bf16_sk2000.md"},
+    ("sk2000", "fp32"): {"source": "paper_1907_05124_amd/csrc/dense_phase.h", "sha256_prefix": "4be37f4594fd5dee",
+                         "fetch_kib": 54899.4, "write_kib": 16000.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                         "summary": "profiles/k_dense_phase_f32_sk2000.md"},
+    ("sk2000", "bf16"): {"source": "paper_1907_05124_amd/csrc/dense_phase_bf16.h", "sha256_prefix": "237f59c1c1e9c87f",
+                         "fetch_kib": 26428.9, "write_kib": 8256.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                         "summary": "profiles/k_dense_phase_bf16_sk2000.md"},
+    ("ea3d_L32", "fp16"): {"source": "paper_1907_05124_amd/csrc/k_lattice.hip", "sha256_prefix": "50cee71e34ba1fef",
+                           "fetch_kib": 1023.1, "write_kib": 65600.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                           "summary": "profiles/k_lattice_solve_ea3d_L32.md"},
+    ("ea2d_L16", "fp32"): {"source": "paper_1907_05124_amd/csrc/k_lattice.hip", "sha256_prefix": "50cee71e34ba1fef",
+                           "fetch_kib": 100.6, "write_kib": 288.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                           "summary": "profiles/k_lattice_solve_ea2d_L16.md"},
+    ("er800", "fp32"): {"source": "paper_1907_05124_amd/csrc/k_sparse.hip", "sha256_prefix": "f7d01860c3adc834",
+                        "fetch_kib": 1179.8, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                        "summary": "profiles/k_sparse_solve_er800.md"},
+    ("er20000", "fp16"): {"source": "paper_1907_05124_amd/csrc/k_sparse.hip", "sha256_prefix": "f7d01860c3adc834",
+                          "fetch_kib": 3406.2, "write_kib": 160373.1, "fetch_scale": 2.0, "write_scale": 1.0,
+                          "summary": "profiles/k_sparse_solve_er20000.md"},
 }
 
 DESCRIPTION = {
@@ -56,8 +70,8 @@ def recorded_traffic(workload, precision):
     """Bytes per launch from the recorded counters, or None if the kernel changed since."""
     import hashlib
 
-    rec = TRAFFIC_RECORD.get(precision)
-    if rec is None or workload != rec["workload"]:
+    rec = TRAFFIC_RECORD.get((workload, precision))
+    if rec is None:
         return None
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_prefix"]:
@@ -373,7 +387,8 @@ def main():
             achieved = flops / per_launch_s / 1e12
             peak = PEAK["fp64_valu"] if prec == "fp64" else PEAK["fp32_valu"]
             out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                               "frac": round(achieved / peak, 4), "traffic": None,
+                               "frac": round(achieved / peak, 4),
+                               "traffic": recorded_traffic(args.workload, prec),
                                "kernel": "k_lattice_solve" if lat else "k_sparse_solve",
                                "launch_us": round(per_launch_s * 1e6, 3), "flops_per_launch": flops}
         return out
