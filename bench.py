@@ -46,10 +46,10 @@ TRAFFIC_RECORD = {
                            "fetch_kib": 100.6, "write_kib": 288.0, "fetch_scale": 2.0, "write_scale": 1.0,
                            "summary": "profiles/k_lattice_solve_ea2d_L16.md"},
     ("er800", "fp32"): {"source": "paper_1907_05124_amd/csrc/k_sparse.hip", "sha256_prefix": "f7d01860c3adc834",
-                        "fetch_kib": 1179.8, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                        "fetch_kib": 1200.5, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
                         "summary": "profiles/k_sparse_solve_er800.md"},
     ("er20000", "fp16"): {"source": "paper_1907_05124_amd/csrc/k_sparse.hip", "sha256_prefix": "f7d01860c3adc834",
-                          "fetch_kib": 3406.2, "write_kib": 160373.1, "fetch_scale": 2.0, "write_scale": 1.0,
+                          "fetch_kib": 3417.6, "write_kib": 165571.5, "fetch_scale": 2.0, "write_scale": 1.0,
                           "summary": "profiles/k_sparse_solve_er20000.md"},
 }
 

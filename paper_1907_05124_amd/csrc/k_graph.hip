@@ -131,9 +131,10 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
             return hip_error(e, "lattice solve launch");
         return MARS_OK;
     }
-    // runs per thread: two when the block has at least two runs (fp32/fp16);
-    // MARS_SPARSE_VEC=1|2|4 overrides (tuning)
-    int vec = (esz <= 4 && rpw >= 2) ? 2 : 1;
+    // runs per thread (fp32/fp16): four when the block has at least four
+    // runs, else two when it has two (each entry group read and decoded once
+    // for all of them); MARS_SPARSE_VEC=1|2|4 overrides (tuning)
+    int vec = esz > 4 ? 1 : rpw >= 4 ? 4 : rpw >= 2 ? 2 : 1;
     const int want = env_int("MARS_SPARSE_VEC", 0);
     if (esz <= 4 && (want == 1 || want == 2 || want == 4) && want <= rpw)
         vec = want;
