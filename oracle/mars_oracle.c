@@ -415,9 +415,30 @@ typedef struct {
     double last_d;
 } orc_run_stats;
 
+/* Per-level records of one run, all optional (cap entries each; level kk of
+ * the visited range at index kk, entries past the run's levels untouched).
+ *   replay  sweeps to run at each level instead of the stopping rule (an
+ *           entry <= 0 keeps the rule at that level): the sweep counts
+ *           another implementation reports, so that its trajectory can be
+ *           followed where its d-versus-d_min decisions differ from this
+ *           one's (Algorithm 1's repeat ... until, decided in another
+ *           precision).
+ *   sweeps  sweeps run at each level.
+ *   own     the sweep at which this oracle's own rule (d < d_min, or the
+ *           max_sweeps cap) ends the level; under replay, count + 1 when the
+ *           rule would not have ended it within the replayed count.
+ *   d_own   the largest change d of sweep min(own, sweeps run). */
+typedef struct {
+    const int32_t *replay;
+    int32_t *sweeps;
+    int32_t *own;
+    double *d_own;
+    int cap;
+} orc_level_io;
+
 /* relax one run in place; m has N entries */
 static void run_one(const orc_instance *in, const orc_schedule *sc, const int32_t *phase_of, int nph,
-                    double T0, double *m, double *phi, orc_run_stats *st)
+                    double T0, double *m, double *phi, orc_run_stats *st, const orc_level_io *io)
 {
     int N = in->N;
     int cap = 0;
@@ -436,6 +457,12 @@ static void run_one(const orc_instance *in, const orc_schedule *sc, const int32_
         double T = lev[k];
         int sweeps = 0;
         double d;
+        const int kk = k - k0;
+        const int rec = io && kk < io->cap;
+        /* the replayed count, or 0 to follow the stopping rule */
+        const int want = (rec && io->replay) ? io->replay[kk] : 0;
+        int own = 0;
+        double d_own = NAN;
         do {
             d = 0.0;
             for (int p = 0; p < nph; ++p) {
@@ -453,9 +480,25 @@ static void run_one(const orc_instance *in, const orc_schedule *sc, const int32_
                     }
             }
             ++sweeps;
-        } while (!(d < sc->d_min) && sweeps < sc->max_sweeps);
+            if (!own && ((d < sc->d_min) || sweeps >= sc->max_sweeps)) {
+                own = sweeps; /* where this oracle's own rule ends the level */
+                d_own = d;
+            }
+        } while (want > 0 ? sweeps < want : (!(d < sc->d_min) && sweeps < sc->max_sweeps));
+        if (!own) {
+            own = sweeps + 1; /* the rule would have run on past the replayed count */
+            d_own = d;
+        }
         if (sc->max_sweeps > 1 && !(d < sc->d_min))
             ++cap; /* a level cut short by the sweep cap */
+        if (rec) {
+            if (io->sweeps)
+                io->sweeps[kk] = sweeps;
+            if (io->own)
+                io->own[kk] = own;
+            if (io->d_own)
+                io->d_own[kk] = d_own;
+        }
         st->sweeps += sweeps;
         st->levels += 1;
         st->last_T = T;
@@ -486,6 +529,7 @@ typedef struct {
     int64_t *levels; /* run_count */
     int64_t *cap_hits; /* run_count */
     double *last_T; /* run_count */
+    orc_level_io lio; /* per-level records, cap entries per run (pointers to run 0's) */
     /* shared */
     const int32_t *phase_of;
     int nph;
@@ -512,7 +556,13 @@ static void *worker(void *arg)
             m[i] = jb->m0 ? jb->m0[(size_t)i * jb->run_count + q] : orc_initial_m(jb->seed, run, i);
         double T0 = jb->T0 ? jb->T0[q] : orc_initial_T(jb->seed, run, jb->sc->T_lo, jb->sc->T_hi);
         orc_run_stats st;
-        run_one(in, jb->sc, jb->phase_of, jb->nph, T0, m, phi, &st);
+        orc_level_io io = jb->lio;
+        const size_t o = (size_t)q * (size_t)(io.cap > 0 ? io.cap : 0);
+        io.replay = io.replay ? io.replay + o : NULL;
+        io.sweeps = io.sweeps ? io.sweeps + o : NULL;
+        io.own = io.own ? io.own + o : NULL;
+        io.d_own = io.d_own ? io.d_own + o : NULL;
+        run_one(in, jb->sc, jb->phase_of, jb->nph, T0, m, phi, &st, io.cap > 0 ? &io : NULL);
         for (int i = 0; i < N; ++i)
             s[i] = (m[i] >= 0.0) ? 1 : -1;
         if (jb->m_final)
@@ -539,9 +589,27 @@ static void *worker(void *arg)
     return NULL;
 }
 
+/* orc_solve with per-level records (see orc_level_io; arrays [run_count x
+ * cap], any pointer NULL; cap = 0 keeps none) */
+int orc_solve_levels(const orc_instance *in, const orc_schedule *sc, uint64_t seed, int run_begin, int run_count,
+                     const double *m0, const double *T0, double *m_final, int8_t *spins, double *energy,
+                     double *T0_out, int64_t *sweeps, int64_t *levels, int64_t *cap_hits, double *last_T,
+                     int nthreads, const int32_t *replay, int32_t *sweeps_per_level, int32_t *own_per_level,
+                     double *d_per_level, int cap);
+
 int orc_solve(const orc_instance *in, const orc_schedule *sc, uint64_t seed, int run_begin, int run_count,
               const double *m0, const double *T0, double *m_final, int8_t *spins, double *energy, double *T0_out,
               int64_t *sweeps, int64_t *levels, int64_t *cap_hits, double *last_T, int nthreads)
+{
+    return orc_solve_levels(in, sc, seed, run_begin, run_count, m0, T0, m_final, spins, energy, T0_out, sweeps,
+                            levels, cap_hits, last_T, nthreads, NULL, NULL, NULL, NULL, 0);
+}
+
+int orc_solve_levels(const orc_instance *in, const orc_schedule *sc, uint64_t seed, int run_begin, int run_count,
+                     const double *m0, const double *T0, double *m_final, int8_t *spins, double *energy,
+                     double *T0_out, int64_t *sweeps, int64_t *levels, int64_t *cap_hits, double *last_T,
+                     int nthreads, const int32_t *replay, int32_t *sweeps_per_level, int32_t *own_per_level,
+                     double *d_per_level, int cap)
 {
     if (!in || !sc || in->N < 1 || run_count < 0)
         return 1;
@@ -563,6 +631,11 @@ int orc_solve(const orc_instance *in, const orc_schedule *sc, uint64_t seed, int
     jb.levels = levels;
     jb.cap_hits = cap_hits;
     jb.last_T = last_T;
+    jb.lio.replay = replay;
+    jb.lio.sweeps = sweeps_per_level;
+    jb.lio.own = own_per_level;
+    jb.lio.d_own = d_per_level;
+    jb.lio.cap = cap < 0 ? 0 : cap;
     jb.nph = orc_phases(in, sc, phase_of);
     jb.phase_of = phase_of;
     pthread_mutex_init(&jb.lock, NULL);

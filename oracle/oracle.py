@@ -69,6 +69,9 @@ def _bind(path):
     L.orc_solve.restype = C.c_int
     L.orc_solve.argtypes = [C.POINTER(_Inst), C.POINTER(_Sched), C.c_uint64, C.c_int, C.c_int] + \
         [C.c_void_p] * 10 + [C.c_int]
+    L.orc_solve_levels.restype = C.c_int
+    L.orc_solve_levels.argtypes = [C.POINTER(_Inst), C.POINTER(_Sched), C.c_uint64, C.c_int, C.c_int] + \
+        [C.c_void_p] * 10 + [C.c_int] + [C.c_void_p] * 4 + [C.c_int]
     L.orc_best.restype = C.c_int
     L.orc_best.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64)]
     return L
@@ -235,12 +238,21 @@ def levels(sched, T0: float) -> np.ndarray:
 
 
 def solve(inst, runs: int, sched, seed: int, *, run_begin: int = 0, run_count: int | None = None,
-          m0=None, T0=None, nthreads: int | None = None) -> dict:
+          m0=None, T0=None, nthreads: int | None = None, levels_cap: int = 0, replay=None) -> dict:
     """Run MARS on runs [run_begin, run_begin + run_count) of a ``runs``-run solve.
 
     Runs are independent, so any subset gives the same per-run results as the
     full solve.  ``m0`` ([N, run_count]) and ``T0`` ([run_count]) replace the
-    generator's draws when given."""
+    generator's draws when given.
+
+    ``levels_cap`` > 0 adds per-level records of the first ``levels_cap``
+    visited levels of every run ([run_count, levels_cap] each; 0 past a run's
+    levels): ``sweeps_per_level``, ``own_per_level`` (where the oracle's own
+    stopping rule ends the level; count + 1 under replay when it would have
+    gone on) and ``d_per_level`` (the largest change of that sweep).
+    ``replay`` ([run_count, levels_cap] int32) runs exactly that many sweeps at
+    each level (entries <= 0: the stopping rule) -- the sweep counts another
+    implementation reports."""
     del runs  # per-run results do not depend on the total
     ci = inst if isinstance(inst, Instance) else Instance(inst)
     N = ci.N
@@ -259,13 +271,25 @@ def solve(inst, runs: int, sched, seed: int, *, run_begin: int = 0, run_count: i
         "cap_hits": np.empty(rc, dtype=np.int64),
         "last_T": np.empty(rc, dtype=np.float64),
     }
+    cap = int(levels_cap)
+    rep = None
+    if replay is not None:
+        if cap < 1:
+            raise ValueError("replay needs levels_cap")
+        rep = np.ascontiguousarray(replay, dtype=np.int32).reshape(rc, cap)
+    if cap > 0:
+        out["sweeps_per_level"] = np.zeros((rc, cap), dtype=np.int32)
+        out["own_per_level"] = np.zeros((rc, cap), dtype=np.int32)
+        out["d_per_level"] = np.zeros((rc, cap), dtype=np.float64)
     if nthreads is None:
         nthreads = os.cpu_count() or 1
-    rcode = lib().orc_solve(C.byref(ci.c), C.byref(_sched(sched)), seed & (2**64 - 1), int(run_begin), rc,
-                            _ptr(m0a), _ptr(T0a), out["m"].ctypes.data, out["spins"].ctypes.data,
-                            out["energy"].ctypes.data, out["T0"].ctypes.data, out["sweeps"].ctypes.data,
-                            out["levels"].ctypes.data, out["cap_hits"].ctypes.data, out["last_T"].ctypes.data,
-                            int(nthreads))
+    rcode = lib().orc_solve_levels(C.byref(ci.c), C.byref(_sched(sched)), seed & (2**64 - 1), int(run_begin), rc,
+                                   _ptr(m0a), _ptr(T0a), out["m"].ctypes.data, out["spins"].ctypes.data,
+                                   out["energy"].ctypes.data, out["T0"].ctypes.data, out["sweeps"].ctypes.data,
+                                   out["levels"].ctypes.data, out["cap_hits"].ctypes.data,
+                                   out["last_T"].ctypes.data, int(nthreads), _ptr(rep),
+                                   _ptr(out.get("sweeps_per_level")), _ptr(out.get("own_per_level")),
+                                   _ptr(out.get("d_per_level")), cap)
     if rcode != 0:
         raise RuntimeError("oracle solve failed")
     return out

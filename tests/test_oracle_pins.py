@@ -265,6 +265,106 @@ def test_zero_couplings_closed_form():
             assert abs(r["m"][i, q] - math.tanh(float(h[i]) / (2 * T0[q]))) < 1e-15
 
 
+@pytest.mark.parametrize("gamma", [0.3, 0.7])
+def test_zero_couplings_damped_closed_form(gamma):
+    """J = 0 with damping g: every sweep moves m a fraction g of the way to the
+    fixed point t = tanh(h / (2T)), so after n sweeps at one temperature
+    m_n = t + (1 - g)^n (m_0 - t) (the closed form of the iterated convex
+    combination; the fixed point itself does not depend on g)."""
+    N, R = 6, 2
+    h = np.array([0.9, -1.3, 0.05, 2.0, -0.4, 0.0], dtype=np.float32)
+    inst = I.DenseInstance(J=np.zeros((N, N), np.float32), h=h)
+    T0 = np.array([0.5, 1.7])
+    m0 = np.array([[0.8, -0.6], [0.1, 0.9], [-0.95, 0.3], [0.0, -0.2], [0.5, 0.5], [-0.7, 0.25]])
+    for n in (1, 2, 5, 17):
+        sch = I.Schedule(T_lo=0.5, T_hi=1.7, steps=1, max_sweeps=n, d_min=0.0, damping=gamma)
+        r = O.solve(inst, R, sch, 0, run_count=R, m0=m0, T0=T0)
+        for q in range(R):
+            for i in range(N):
+                t = math.tanh(float(h[i]) / (2 * T0[q]))
+                want = t + (1 - gamma) ** n * (m0[i, q] - t)
+                assert abs(r["m"][i, q] - want) < 1e-14, (n, q, i)
+        # d_min = 0 is never undercut: the cap ends the level
+        assert np.all(r["sweeps"] == n) and np.all(r["cap_hits"] == (1 if n > 1 else 0))
+
+
+@pytest.mark.parametrize("gamma", [0.3, 0.7])
+def test_damped_sweep_count_closed_form(gamma):
+    """J = 0 with damping: the change of sweep n is g (1 - g)^(n-1) |m_0 - t|
+    (largest over the spins), so the level ends at the first n where that is
+    below d_min -- a count fixed in closed form, which pins the stopping rule
+    of the repeat ... until loop and the per-level sweep record."""
+    N = 4
+    h = np.array([1.0, -0.5, 0.25, 0.0], dtype=np.float32)
+    inst = I.DenseInstance(J=np.zeros((N, N), np.float32), h=h)
+    T = 0.8
+    m0 = np.array([[0.3], [0.9], [-0.6], [0.45]])
+    t = np.tanh(h.astype(np.float64) / (2 * T))
+    dev = float(np.max(np.abs(m0[:, 0] - t)))
+    for d_min in (1e-2, 1e-4, 1e-7):
+        n = 1
+        while not (gamma * (1 - gamma) ** (n - 1) * dev < d_min):
+            n += 1
+        sch = I.Schedule(T_lo=T, T_hi=T, steps=1, max_sweeps=10000, d_min=d_min, damping=gamma)
+        r = O.solve(inst, 1, sch, 0, run_count=1, m0=m0, T0=np.array([T]), levels_cap=2)
+        assert int(r["sweeps"][0]) == n and int(r["cap_hits"][0]) == 0, (d_min, n, r["sweeps"])
+        assert r["sweeps_per_level"][0, 0] == n and r["own_per_level"][0, 0] == n
+        assert r["sweeps_per_level"][0, 1] == 0  # one level only
+        # a cap below n ends the level early and is counted; max_sweeps = 1 is
+        # one sweep per level by definition and counts no cap
+        for cap in (1, 2, n - 1):
+            if cap < 1 or cap >= n:
+                continue
+            sc2 = I.Schedule(T_lo=T, T_hi=T, steps=1, max_sweeps=cap, d_min=d_min, damping=gamma)
+            r2 = O.solve(inst, 1, sc2, 0, run_count=1, m0=m0, T0=np.array([T]))
+            assert int(r2["sweeps"][0]) == cap
+            assert int(r2["cap_hits"][0]) == (1 if cap > 1 else 0), (cap, n)
+
+
+def test_cap_hits_count_levels_cut_by_the_cap():
+    """Over a whole schedule, cap_hits is the number of levels the sweep cap
+    ended: every level when d_min = 0 (never undercut) and max_sweeps > 1,
+    none when each level converges within the cap, none when max_sweeps = 1."""
+    inst = I.DenseInstance(J=np.array([[0, 0.9], [0.9, 0]], dtype=np.float32))
+    T0 = np.array([1.3, 2.9, 0.7])
+    m0 = np.array([[0.6, -0.2, 0.9], [0.1, 0.4, -0.3]])
+    sch = I.Schedule(kind="linear", T_lo=0.5, T_hi=3.0, c_step=0.1, max_sweeps=3, d_min=0.0, phases=2)
+    r = O.solve(inst, 3, sch, 0, run_count=3, m0=m0, T0=T0)
+    assert np.all(r["levels"] > 0) and np.array_equal(r["cap_hits"], r["levels"])
+    assert np.array_equal(r["sweeps"], 3 * r["levels"])
+    sch1 = I.Schedule(kind="linear", T_lo=0.5, T_hi=3.0, c_step=0.1, max_sweeps=1, d_min=0.0, phases=2)
+    r1 = O.solve(inst, 3, sch1, 0, run_count=3, m0=m0, T0=T0)
+    assert np.all(r1["cap_hits"] == 0) and np.array_equal(r1["sweeps"], r1["levels"])
+    sch2 = I.Schedule(kind="linear", T_lo=0.5, T_hi=3.0, c_step=0.1, max_sweeps=100000, d_min=1e-6, phases=2)
+    r2 = O.solve(inst, 3, sch2, 0, run_count=3, m0=m0, T0=T0)
+    assert np.all(r2["cap_hits"] == 0) and np.all(r2["sweeps"] > r2["levels"])
+
+
+def test_replay_of_own_counts_and_of_other_counts():
+    """Replaying the oracle's own per-level sweep counts reproduces its run bit
+    for bit; replaying one sweep per level equals the max_sweeps = 1 schedule;
+    under a replay the own-rule record marks exactly the levels whose replayed
+    count differs from the rule's, with the d of the deciding sweep."""
+    inst = I.sk_instance(40, 8)
+    s = I.field_scale(inst)
+    sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=3 * s, c_step=0.3 * s, max_sweeps=500, d_min=1e-4, phases=2)
+    R, cap = 6, 16
+    r = O.solve(inst, R, sch, 11, run_count=R, levels_cap=cap)
+    assert np.array_equal(r["sweeps_per_level"].sum(axis=1), r["sweeps"])
+    assert np.array_equal(r["own_per_level"], r["sweeps_per_level"])
+    assert np.all(r["d_per_level"][r["sweeps_per_level"] > 0] < 1e-4)
+    rr = O.solve(inst, R, sch, 11, run_count=R, levels_cap=cap, replay=r["sweeps_per_level"])
+    assert np.array_equal(rr["m"], r["m"]) and np.array_equal(rr["sweeps"], r["sweeps"])
+    ones = np.where(r["sweeps_per_level"] > 0, 1, 0).astype(np.int32)
+    r1 = O.solve(inst, R, sch, 11, run_count=R, levels_cap=cap, replay=ones)
+    sc1 = I.Schedule(kind="linear", T_lo=0.0, T_hi=3 * s, c_step=0.3 * s, max_sweeps=1, d_min=1e-4, phases=2)
+    ref1 = O.solve(inst, R, sc1, 11, run_count=R)
+    assert np.array_equal(r1["m"], ref1["m"])
+    live = r["sweeps_per_level"] > 1
+    # with one sweep replayed where the rule needs more, the rule would go on
+    assert np.all(r1["own_per_level"][live] == 2) and np.all(r1["d_per_level"][live] >= 1e-4)
+
+
 def test_single_spin():
     """N = 1: no couplings, the field is zero, m becomes 0 and rounds to +1 with E = 0."""
     inst = I.DenseInstance(J=np.zeros((1, 1), np.float32))
@@ -300,12 +400,15 @@ def _free_energy(Jd, h, m, T):
     return e - 2 * T * S.sum()
 
 
-@pytest.mark.parametrize("inst_kind", ["lattice2d", "lattice3d", "er"])
-def test_free_energy_is_nonincreasing_over_sweeps(inst_kind):
+@pytest.mark.parametrize("inst_kind,gamma", [("lattice2d", 1.0), ("lattice3d", 1.0), ("er", 1.0),
+                                             ("lattice2d", 0.3), ("er", 0.7)])
+def test_free_energy_is_nonincreasing_over_sweeps(inst_kind, gamma):
     """Updating an independent set of spins (a lattice sublattice or a colour
     class) minimises the mean-field free energy over them, so F never rises
-    from sweep to sweep at fixed T.  A sign error in the field or the update,
-    or a wrong neighbour, breaks this."""
+    from sweep to sweep at fixed T.  F is convex in each such spin, so a damped
+    step (a convex combination of the old value and the minimiser) cannot
+    raise it either.  A sign error in the field or the update, or a wrong
+    neighbour, breaks this."""
     if inst_kind == "lattice2d":
         inst = I.lattice_instance((8, 8), 2)
         Jd = I.lattice_dense(inst).J.astype(np.float64)
@@ -320,7 +423,7 @@ def test_free_energy_is_nonincreasing_over_sweeps(inst_kind):
     for T in (0.3, 1.0, 2.5):
         prev = None
         for sweeps in range(1, 12):
-            sch = I.Schedule(T_lo=T, T_hi=T, steps=1, max_sweeps=sweeps, d_min=0.0)
+            sch = I.Schedule(T_lo=T, T_hi=T, steps=1, max_sweeps=sweeps, d_min=0.0, damping=gamma)
             r = O.solve(inst, 3, sch, 0, run_count=3, m0=m0, T0=np.full(3, T))
             F = np.array([_free_energy(Jd, None, r["m"][:, q], T) for q in range(3)])
             if prev is not None:
