@@ -120,6 +120,10 @@ typedef struct {
     int64_t spin_updates;    /* N x sweeps_executed: magnetisation recomputations */
     int64_t cap_hits;        /* levels ended by max_sweeps (> 1) with d >= d_min */
     int64_t levels_executed; /* levels summed over runs */
+    double seconds;          /* device time of the solve: from its first enqueued
+                                kernel to the best-of-runs step (the device's
+                                constant-rate clock), queueing behind earlier
+                                work on the stream excluded */
 } mars_result;
 
 /* Create a dense instance (paper eq. (2); the SK model of the section "Ising
@@ -175,13 +179,24 @@ mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *s
  *   spins    [runs x N] int8 rounded spins of every run.
  *   energies [runs] double exact energies.
  *   best_spins [N] int8 spins of the best run.
+ *   sweeps_per_level [runs x level_cap] int32: entry (r, k) is the number of
+ *            sweeps run r ran at the k-th level it visited (Algorithm 1's
+ *            repeat ... until loop: the sweep at which the largest change d
+ *            fell below d_min, or max_sweeps; 1 on every level when
+ *            max_sweeps = 1), 0 past the run's last level; levels beyond
+ *            level_cap are not recorded.  These are the decisions a CPU
+ *            reference replays to follow the same trajectory where its own
+ *            d-versus-d_min decisions (taken in another precision) differ.
+ *   level_cap >= 1 when sweeps_per_level is given (ignored otherwise).
  * stream is a hipStream_t (NULL: the default stream).  When res (HOST) is
  * non-NULL the call waits for the stream and fills it; otherwise it returns
  * after enqueueing.  Device outputs are valid once the stream reaches the end
- * of the enqueued work.  Errors as mars_solve. */
+ * of the enqueued work.  Errors as mars_solve, and MARS_E_ARG for
+ * sweeps_per_level with level_cap < 1. */
 mars_status mars_solve_ex(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
                           const void *m0, const double *T0, double *T0_used, void *m_final, int8_t *spins,
-                          double *energies, int8_t *best_spins, mars_result *res, void *stream);
+                          double *energies, int8_t *best_spins, int32_t *sweeps_per_level, int32_t level_cap,
+                          mars_result *res, void *stream);
 
 /* Asynchronous solve for serving many instances concurrently: as
  * mars_solve_ex, but the summary is copied into res_pinned (HOST memory

@@ -11,9 +11,18 @@
 // MFMA.  J is symmetric, so the slab J[k0:k0+32, i0:i0+128] read row-wise is
 // the transposed A tile: both operands arrive as [k][128] rows with
 // coalesced 16-byte loads and sit in LDS k-major, where every MFMA operand
-// read is 32 consecutive floats per half-wave.  All fragments of a slab are
-// read from LDS into registers before its MFMAs are issued, so LDS latency
-// overlaps the matrix pipeline instead of preceding every MFMA.
+// read is 32 consecutive floats per half-wave.  The fragments of half a slab
+// are read from LDS into registers before its MFMAs are issued, so LDS
+// latency overlaps the matrix pipeline instead of preceding every MFMA.
+//
+// Accumulation: the matrix cores add each slab's 32 products per element in
+// fp32; the slab's sum is then added to an fp64 total and the fp32
+// accumulator restarts at zero.  The rounding of the field thus grows with
+// the 16 additions of one slab instead of the N/2 additions of the whole row
+// (for N = 2000, about 4 units in the last place of the field instead of
+// ~30), which keeps the fp32 form's trajectories close to an fp64 evaluation
+// of Algorithm 1 through the low temperatures of the last levels, where 1/T
+// amplifies every change of the field.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,13 +35,27 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int DBM = 128, DBN = 128, DBK = 32;
 
+// tanh in fp64 as expm1(2|a|) / (expm1(2|a|) + 2) with the sign of a
+// (accurate to a few ulp near 0 through expm1; |a| > 20 is +-1 in double)
+__device__ inline double dense_tanh64(double a)
+{
+    const double x = fabs(a);
+    const double e = expm1(2.0 * x);
+    const double t = x > 20.0 ? 1.0 : e / (e + 2.0);
+    return copysign(t, a);
+}
+
 // RAW: instead of the update, write the field Phi = J M + h/2 of the
 // phase's rows to phi (same layout as M) for a sequential pass over them.
+// invT64 (or null): the runs' 1/T in fp64 (same layout as invT); with it the
+// update's argument (Phi + h/2) / T and the tanh are evaluated in fp64 and
+// only the new magnetisation is rounded to fp32.
 template <int WM, int WN, int PF, bool RAW>
 __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
     const float *__restrict__ J, int ldj, const float *__restrict__ Mold, float *__restrict__ Mnew, int ldm, int R,
     int p0, int p1, int a0, int nrt, int nct, int kpad, const float *__restrict__ invT,
-    const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax, float *__restrict__ phi)
+    const double *__restrict__ invT64, const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax,
+    float *__restrict__ phi)
 {
     constexpr int NT = 64 * WM * WN;
     constexpr int TM = DBM / WM, TN = DBN / WN;  // wave sub-tile
@@ -63,13 +86,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
     const int c0 = ct * DBN;
 
     floatx16 acc[MB][NB];
+    double tot[MB][NB][16];
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int v = 0; v < 16; ++v)
+            for (int v = 0; v < 16; ++v) {
                 acc[a][b][v] = 0.0f;
+                tot[a][b][v] = 0.0;
+            }
 
     const int lrow = tid >> 5;        // slab row of this thread's first load
     const int lcol = (tid & 31) * 4;  // column (float4 granularity)
@@ -97,17 +123,27 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
     }
 #define DP_MMA(buf)                                                                                           \
     {                                                                                                         \
-        float fa_[DBK / 2][MB], fb_[DBK / 2][NB];                                                             \
-        _Pragma("unroll") for (int kk = 0; kk < DBK / 2; ++kk)                                                \
+        _Pragma("unroll") for (int hk = 0; hk < 2; ++hk)                                                      \
         {                                                                                                     \
-            const int kr_ = 2 * kk + ka;                                                                      \
-            _Pragma("unroll") for (int a = 0; a < MB; ++a) fa_[kk][a] = As[(buf)][kr_][wm * TM + a * 32 + li]; \
-            _Pragma("unroll") for (int b = 0; b < NB; ++b) fb_[kk][b] = Bs[(buf)][kr_][wn * TN + b * 32 + li]; \
+            float fa_[DBK / 4][MB], fb_[DBK / 4][NB];                                                         \
+            _Pragma("unroll") for (int kk = 0; kk < DBK / 4; ++kk)                                            \
+            {                                                                                                 \
+                const int kr_ = 2 * (hk * (DBK / 4) + kk) + ka;                                               \
+                _Pragma("unroll") for (int a = 0; a < MB; ++a) fa_[kk][a] = As[(buf)][kr_][wm * TM + a * 32 + li]; \
+                _Pragma("unroll") for (int b = 0; b < NB; ++b) fb_[kk][b] = Bs[(buf)][kr_][wn * TN + b * 32 + li]; \
+            }                                                                                                 \
+            _Pragma("unroll") for (int kk = 0; kk < DBK / 4; ++kk)                                            \
+                _Pragma("unroll") for (int a = 0; a < MB; ++a)                                                \
+                    _Pragma("unroll") for (int b = 0; b < NB; ++b)                                            \
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa_[kk][a], fb_[kk][b], acc[a][b], 0, 0, 0); \
         }                                                                                                     \
-        _Pragma("unroll") for (int kk = 0; kk < DBK / 2; ++kk)                                                \
-            _Pragma("unroll") for (int a = 0; a < MB; ++a)                                                    \
-                _Pragma("unroll") for (int b = 0; b < NB; ++b)                                                \
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa_[kk][a], fb_[kk][b], acc[a][b], 0, 0, 0); \
+        _Pragma("unroll") for (int a = 0; a < MB; ++a)                                                        \
+            _Pragma("unroll") for (int b = 0; b < NB; ++b)                                                    \
+                _Pragma("unroll") for (int v = 0; v < 16; ++v)                                                \
+                {                                                                                             \
+                    tot[a][b][v] += (double)acc[a][b][v];                                                     \
+                    acc[a][b][v] = 0.0f;                                                                      \
+                }                                                                                             \
     }
 
     DP_LOAD(xa, xb, 0);
@@ -160,7 +196,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
                 for (int v = 0; v < 16; ++v) {
                     const int row = i0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * ka + (v & 3);
                     if (col < R && row >= p0 && row < p1)
-                        phi[(size_t)row * ldm + col] = acc[a][b][v] + (hhalf ? hhalf[row] : 0.0f);
+                        phi[(size_t)row * ldm + col] = (float)(tot[a][b][v] + (hhalf ? (double)hhalf[row] : 0.0));
                 }
         }
         return;
@@ -174,10 +210,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
     // overlap instead of one round trip per element.
     const bool damp = gamma != 1.0f;
     float itv[NB], ov[NB][MB][16], hv[MB][16];
+    double itd[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int col = c0 + wn * TN + b * 32 + li;
         itv[b] = invT[col];
+        itd[b] = invT64 ? invT64[col] : (double)itv[b];
 #pragma unroll
         for (int a = 0; a < MB; ++a)
 #pragma unroll
@@ -187,8 +225,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
+        for (int v = 0; v < 16; ++v) {
             hv[a][v] = hhalf ? hhalf[i0 + wm * TM + a * 32 + 8 * (v >> 2) + 4 * ka + (v & 3)] : 0.0f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                tot[a][b][v] += (double)hv[a][v];
+        }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int col = c0 + wn * TN + b * 32 + li;
@@ -204,7 +246,11 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
                         const float old = ov[b][a][v];
                         float nw = old;
                         if (it >= 0.0f) {
-                            const float th = tanhf((acc[a][b][v] + hv[a][v]) * it);
+                            float th;
+                            if (invT64)
+                                th = (float)dense_tanh64(tot[a][b][v] * itd[b]);
+                            else
+                                th = tanhf((float)tot[a][b][v] * it);
                             nw = damp ? (1.0f - gamma) * old + gamma * th : th;
                         }
                         Mnew[(size_t)row * ldm + col] = nw;

@@ -85,7 +85,8 @@ void launch_level_table(const mars_schedule &sc, int R, const double *T0, int km
 constexpr int ARG_NT = 1024;
 
 __global__ __launch_bounds__(ARG_NT) void k_argmin(const double *E, const double *T0, const int64_t *runstat, int R,
-                                                   int N, double wsum, mars_result *res, int32_t *best_out)
+                                                   int N, double wsum, mars_result *res, int32_t *best_out,
+                                                   double tick_s)
 {
     __shared__ double sE[ARG_NT];
     __shared__ int sI[ARG_NT];
@@ -153,15 +154,26 @@ __global__ __launch_bounds__(ARG_NT) void k_argmin(const double *E, const double
         res->spin_updates = sCnt[0][0] * (long long)N;
         res->levels_executed = sCnt[1][0];
         res->cap_hits = sCnt[2][0];
+        const uint64_t t0 = *result_stamp(res);
+        res->seconds = (double)((uint64_t)wall_clock64() - t0) * tick_s;
         *best_out = bidx;
     }
 }
 
 void launch_argmin(const double *E, const double *T0, const int64_t *runstat, int R, int N, double wsum,
-                   mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+                   mars_result *res_dev, int32_t *best_dev, double tick_s, hipStream_t s)
 {
-    k_argmin<<<1, ARG_NT, 0, s>>>(E, T0, runstat, R, N, wsum, res_dev, best_dev);
+    k_argmin<<<1, ARG_NT, 0, s>>>(E, T0, runstat, R, N, wsum, res_dev, best_dev, tick_s);
 }
+
+// the device's constant-rate clock at this point of the stream
+__global__ void k_stamp(uint64_t *slot)
+{
+    if (threadIdx.x == 0)
+        *slot = (uint64_t)wall_clock64();
+}
+
+void launch_stamp(uint64_t *slot, hipStream_t s) { k_stamp<<<1, 64, 0, s>>>(slot); }
 
 __global__ void k_gather_best(const int8_t *spins, int ld, const int32_t *best, int N, int8_t *out)
 {

@@ -47,15 +47,15 @@ void launch_dense_init_state(uint64_t seed, int N, int R, int ldm, const float *
 constexpr int DWM = 4, DWN = 4, DPF = 2;
 
 void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, int ldm, int R, int p0, int p1,
-                            const float *invT, float gamma, uint32_t *dmax, hipStream_t s)
+                            const float *invT, const double *invT64, float gamma, uint32_t *dmax, hipStream_t s)
 {
     const int a0 = p0 & ~3;
     const int nrt = (p1 - a0 + DBM - 1) / DBM;
     const int nct = ldm / DBN;
     const int kpad = (I.N + DBK - 1) / DBK * DBK;
     k_dense_phase_f32<DWM, DWN, DPF, false><<<nrt * nct, 64 * DWM * DWN, 0, s>>>(
-        I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma, dmax,
-        nullptr);
+        I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, invT64, I.has_h ? I.hhalf : nullptr, gamma,
+        dmax, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -122,8 +122,8 @@ void launch_dense_seq_block(const Instance &I, const float *Mold, float *Mnew, f
     const int nct = ldm / DBN;
     const int kpad = (I.N + DBK - 1) / DBK * DBK;
     k_dense_phase_f32<DWM, DWN, DPF, true><<<nrt * nct, 64 * DWM * DWN, 0, s>>>(
-        I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, I.has_h ? I.hhalf : nullptr, gamma, dmax,
-        phi);
+        I.J, I.Np, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, nullptr, I.has_h ? I.hhalf : nullptr, gamma,
+        dmax, phi);
     k_dense_seq_block<<<(R + 63) / 64, 64, 0, s>>>(I.J, I.Np, phi, Mold, Mnew, ldm, R, p0, p1, invT, gamma, dmax);
 }
 
@@ -199,14 +199,17 @@ void launch_dense_runstat(int R, const int32_t *nlev, int64_t *runstat, hipStrea
 // temperature of the run's current level, -1 for a finished run (its
 // magnetisations are then left unchanged by the phase kernel).
 
-__global__ void k_dense_advance_init(int R, const float *table, const int32_t *nlev, float *invT_cur,
-                                     int32_t *state, int64_t *runstat, uint32_t *dmax)
+__global__ void k_dense_advance_init(int R, const float *table, const double *table64, const int32_t *nlev,
+                                     float *invT_cur, double *invT64_cur, int32_t *state, int64_t *runstat,
+                                     uint32_t *dmax)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R)
         return;
     const bool any = nlev[r] > 0;
     invT_cur[r] = any ? table[r] : -1.0f;
+    if (table64)
+        invT64_cur[r] = any ? table64[r] : -1.0;
     state[2 * r] = 0;
     state[2 * r + 1] = any ? 0 : -1;
     runstat[(size_t)r * 4 + 0] = 0;
@@ -216,17 +219,20 @@ __global__ void k_dense_advance_init(int R, const float *table, const int32_t *n
     dmax[r] = 0u;
 }
 
-void launch_dense_advance_init(int R, const float *table, const int32_t *nlev, float *invT_cur, int32_t *state,
-                               int64_t *runstat, uint32_t *dmax, hipStream_t s)
+void launch_dense_advance_init(int R, const float *table, const double *table64, const int32_t *nlev,
+                               float *invT_cur, double *invT64_cur, int32_t *state, int64_t *runstat, uint32_t *dmax,
+                               hipStream_t s)
 {
-    k_dense_advance_init<<<(R + 255) / 256, 256, 0, s>>>(R, table, nlev, invT_cur, state, runstat, dmax);
+    k_dense_advance_init<<<(R + 255) / 256, 256, 0, s>>>(R, table, table64, nlev, invT_cur, invT64_cur, state,
+                                                          runstat, dmax);
 }
 
 // After a sweep: a level ends when the sweep's largest change d is below
 // d_min or after max_sweeps sweeps; the run then moves to its next level.
-__global__ void k_dense_advance(int R, const float *table, int ldt, const int32_t *nlev, int max_sweeps,
-                                double d_min, float *invT_cur, int32_t *state, int64_t *runstat, uint32_t *dmax,
-                                uint32_t *active)
+// spl (or null): [R x cap] sweeps run at each visited level of each run.
+__global__ void k_dense_advance(int R, const float *table, const double *table64, int ldt, const int32_t *nlev,
+                                int max_sweeps, double d_min, float *invT_cur, double *invT64_cur, int32_t *state,
+                                int64_t *runstat, uint32_t *dmax, uint32_t *active, int32_t *spl, int cap)
 {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R)
@@ -243,14 +249,20 @@ __global__ void k_dense_advance(int R, const float *table, int ldt, const int32_
         if (!conv && max_sweeps > 1)
             runstat[(size_t)r * 4 + 2] += 1;
         runstat[(size_t)r * 4 + 1] += 1;
+        if (spl && state[2 * r] < cap)
+            spl[(size_t)r * cap + state[2 * r]] = sw;
         const int lv = state[2 * r] + 1;
         state[2 * r] = lv;
         sw = 0;
         if (lv >= nlev[r]) {
             sw = -1;
             invT_cur[r] = -1.0f;
+            if (table64)
+                invT64_cur[r] = -1.0;
         } else {
             invT_cur[r] = table[(size_t)lv * ldt + r];
+            if (table64)
+                invT64_cur[r] = table64[(size_t)lv * ldt + r];
         }
     }
     state[2 * r + 1] = sw;
@@ -258,12 +270,27 @@ __global__ void k_dense_advance(int R, const float *table, int ldt, const int32_
         atomicAdd(active, 1u);
 }
 
-void launch_dense_advance(int R, const float *table, int ldt, const int32_t *nlev, int max_sweeps, double d_min,
-                          float *invT_cur, int32_t *state, int64_t *runstat, uint32_t *dmax, uint32_t *active,
-                          hipStream_t s)
+void launch_dense_advance(int R, const float *table, const double *table64, int ldt, const int32_t *nlev,
+                          int max_sweeps, double d_min, float *invT_cur, double *invT64_cur, int32_t *state,
+                          int64_t *runstat, uint32_t *dmax, uint32_t *active, int32_t *spl, int cap, hipStream_t s)
 {
-    k_dense_advance<<<(R + 255) / 256, 256, 0, s>>>(R, table, ldt, nlev, max_sweeps, d_min, invT_cur, state,
-                                                     runstat, dmax, active);
+    k_dense_advance<<<(R + 255) / 256, 256, 0, s>>>(R, table, table64, ldt, nlev, max_sweeps, d_min, invT_cur,
+                                                     invT64_cur, state, runstat, dmax, active, spl, cap);
+}
+
+// One sweep per level: every visited level of run r ran one sweep.
+__global__ void k_dense_spl_ones(int R, const int32_t *nlev, int32_t *spl, int cap)
+{
+    const int r = blockIdx.y;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R && k < cap)
+        spl[(size_t)r * cap + k] = k < nlev[r] ? 1 : 0;
+}
+
+void launch_dense_spl_ones(int R, const int32_t *nlev, int32_t *spl, int cap, hipStream_t s)
+{
+    dim3 grid((cap + 255) / 256, R);
+    k_dense_spl_ones<<<grid, 256, 0, s>>>(R, nlev, spl, cap);
 }
 
 // ---------------------------------------------------------------------------

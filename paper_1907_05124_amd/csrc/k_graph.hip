@@ -109,6 +109,8 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     a.m_final = g.m_final;
     a.spins = g.spins;
     a.runstat = g.runstat;
+    a.spl = g.spl;
+    a.spl_cap = g.spl ? g.spl_cap : 0;
 
     hipError_t e;
     const RunSchedule rs = make_run_schedule(sc);

@@ -33,7 +33,7 @@ template <typename S, int VEC, int DIM, bool JAC, bool TRACKD, bool HAS_H, bool 
 __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
 {
     typedef typename LStore<S>::C C;
-    extern __shared__ unsigned char smem_raw[];
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int N = a.N;
     const int rpw = 1 << lg_rpw;
     S *m = reinterpret_cast<S *>(smem_raw);
@@ -119,21 +119,29 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
     const uint32_t oxp1 = ob(xh < H - 1 ? 1 : 1 - L0), oxm1 = ob(-1);
     const uint32_t cyp = ob(cy + 1 < L1 ? L0 : L0 - plane), cym = ob(cy > 0 ? -L0 : plane - L0);
 
+    // (16 bytes, 16-aligned: the dynamic area that holds the state follows the
+    // static one, and the state's 16-byte reads need it 16-aligned)
+    __shared__ __attribute__((aligned(16))) unsigned vote[4];
+    if (threadIdx.x == 0)
+        vote[0] = vote[1] = 0u;
     __syncthreads();
-    for (;;) {
+    for (unsigned nvote = 0;; ++nvote) {
         // the runs' level state, advanced at the end of the previous sweep
         C scale[VEC];
         bool done[VEC];
-        bool any = false, all = true;
+        unsigned code = 0;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
             scale[e] = run_tscale<C>(rsl[q0 + e]);
             done[e] = rsl[q0 + e].done != 0;
-            any |= !done[e];
-            all &= !done[e];
+            code |= done[e] ? 2u : 1u;
         }
-        if (!__syncthreads_or(any))
+        // block-uniform: leave when no run of the block anneals; the fast
+        // update only while every run of the block does
+        const unsigned v = block_vote(vote, nvote, code);
+        if (!(v & 1u))
             break;
+        const bool all = !(v & 2u);
         C dloc[VEC];
 #pragma unroll
         for (int e = 0; e < VEC; ++e)
@@ -222,14 +230,14 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
             if constexpr (FAST) {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
-                    nw.v[e] = LStore<S>::st(l_tanh_run(phi[e], scale[e]));
+                    nw.v[e] = LStore<S>::st(l_tanh_run<sizeof(S) == 4>(phi[e], scale[e]));
                 lds_put<S, VEC>(reinterpret_cast<S *>(wb + vb), nw);
                 return;
             }
             const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + vb));
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                const C th = l_tanh_run(phi[e], scale[e]);
+                const C th = l_tanh_run<sizeof(S) == 4>(phi[e], scale[e]);
                 const C o = LStore<S>::ld(old.v[e]);
                 C n = DAMP ? ((C)1 - g) * o + g * th : th;
                 n = done[e] ? o : n;  // a finished run keeps its state
@@ -413,9 +421,15 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
         // schedules) on its own lane of the first wave, side by side
         for (int q = threadIdx.x; q < rpw; q += blockDim.x) {
             rsl[q].end_sweep(a.rs, __uint_as_float(dq[q]), TRACKD, a.max_sweeps, a.d_min,
-                             ttab ? tT + (size_t)q * ttab : nullptr, ttab ? tI + (size_t)q * ttab : nullptr);
+                             ttab ? tT + (size_t)q * ttab : nullptr, ttab ? tI + (size_t)q * ttab : nullptr,
+                             a.spl ? a.spl + (size_t)(blockIdx.x * rpw + q) * a.spl_cap : nullptr, a.spl_cap);
             dq[q] = 0;
         }
+        // Keep this barrier.  Without it (the run-owning lanes feeding the
+        // next sweep's vote directly) a build hung the GPU on a 2D fp32
+        // lattice with 200 runs: the compiler split the sweep loop into a
+        // nest in which owner and non-owner lanes of one wave took different
+        // paths through the code holding the barriers.
         __syncthreads();
     }
 

@@ -155,14 +155,18 @@ struct RunState {
         }
     }
     // d: the run's largest change in the sweep (fp32 image), read only when
-    // several sweeps per level are allowed
+    // several sweeps per level are allowed.  spl: the run's row of per-level
+    // sweep counts (entry = index of the level among those visited), cap
+    // entries, or null
     __device__ void end_sweep(const RunSchedule &rs, float d, bool trackd, int max_sweeps, double d_min,
-                              const double *tT, const float *tI)
+                              const double *tT, const float *tI, int32_t *spl, int cap)
     {
         if (done)
             return;
         ++sweeps;
         if (!trackd) {
+            if (spl && levels < cap)
+                spl[levels] = 1;
             advance(rs, tT, tI);
             return;
         }
@@ -171,6 +175,8 @@ struct RunState {
         if (conv || sw >= max_sweeps) {
             if (!conv && max_sweeps > 1)
                 ++caps;
+            if (spl && levels < cap)
+                spl[levels] = sw;
             advance(rs, tT, tI);
         }
     }
@@ -183,6 +189,31 @@ struct RunState {
     }
 };
 
+// Block-wide vote at the top of a sweep of an LDS-resident solver: every
+// thread contributes code bit 0 (one of its runs still anneals) and bit 1 (one
+// of its runs has finished); the OR over the block comes back to every thread
+// (every lane of the workgroup must call it, with the whole wave active),
+// so the branches taken on it (leave the sweep loop; the fast update that
+// needs every run live) are the same for the whole workgroup and every thread
+// meets the same barriers.  One barrier per vote: the two words serve
+// alternate votes, and the word of the next vote is cleared after this one's
+// barrier, by which time every thread has read the previous vote from it (a
+// sweep holds at least one more barrier between two votes).  words[0..1] must
+// be zero before the first vote, k counts the votes.
+__device__ inline unsigned block_vote(unsigned *words, unsigned k, unsigned code)
+{
+    unsigned *w = words + (k & 1u);
+    // one LDS atomic per wave (the lanes' codes combined by two ballots)
+    const unsigned wc = (__ballot(code & 1u) ? 1u : 0u) | (__ballot(code & 2u) ? 2u : 0u);
+    if ((threadIdx.x & 63u) == 0u && wc)
+        atomicOr(w, wc);
+    __syncthreads();
+    const unsigned v = *w;
+    if (threadIdx.x == 0)
+        words[(k + 1u) & 1u] = 0u;
+    return v;
+}
+
 // Per-run LDS area of an LDS-resident solver: state, then the sweep's
 // largest change (bit pattern of a non-negative float, for atomicMax).
 constexpr size_t RUN_AREA_BYTES = sizeof(RunState) + sizeof(uint32_t);
@@ -194,15 +225,40 @@ static_assert(RUN_AREA_BYTES <= RUN_AREA_MAX, "per-run LDS area exceeds the laun
 // a large argument is +inf and its reciprocal 0, so the ends are exactly -1
 // and +1; absolute error ~1e-7 near 0, as for the form on |a|); fp64 divides
 // by T
+//
+// ACCURATE (fp32 storage): the form above has an absolute error of ~1e-7
+// (the rounding of 2 / (1 + e) near 1), a large relative error where
+// tanh(a) is small: it returns exactly 0 once |a| < ~3e-8, which would pin a
+// magnetisation that decayed at a high temperature at 0 for the rest of the
+// anneal (tanh keeps it tiny and lets it grow back once T falls below the
+// instability), and it perturbs every small magnetisation by much more than
+// fp32 rounding.  Below |a| = 0.625 tanh(a) = a q(a^2) instead, q a degree-4
+// polynomial fitted for relative error (2.1e-7 with fp32 evaluation, against
+// 2.8e-7 for the exp form above 0.625), so the result carries a relative
+// error of a few fp32 units everywhere.  fp16 storage rounds to 2^-11 anyway
+// and keeps the short form.
+template <bool ACCURATE = false>
 __device__ inline float l_tanh_run(float phi, float ts)
 {
-    const float e = __builtin_amdgcn_exp2f(-phi * ts);
-    return __builtin_fmaf(2.0f, __builtin_amdgcn_rcpf(1.0f + e), -1.0f);
+    const float x = -phi * ts;
+    const float e = __builtin_amdgcn_exp2f(x);
+    const float t = __builtin_fmaf(2.0f, __builtin_amdgcn_rcpf(1.0f + e), -1.0f);
+    if constexpr (ACCURATE) {
+        const float a = x * -0.34657359027997264f;  // x = -2 log2(e) a, so a = -x ln(2) / 2
+        const float z = a * a;
+        float q = __builtin_fmaf(z, 0.015050967f, -0.051821887f);
+        q = __builtin_fmaf(z, q, 0.13304527f);
+        q = __builtin_fmaf(z, q, -0.33331954f);
+        q = __builtin_fmaf(z, q, 0.99999988f);
+        return fabsf(a) < 0.625f ? a * q : t;
+    }
+    return t;
 }
 // fp64: a = Phi * (1/T) (within an ulp of Phi / T, without a division per
 // update), tanh(a) = expm1(2|a|) / (expm1(2|a|) + 2) with the sign of a
 // (accurate near 0 through expm1; a few ulp), a third of the instructions
 // of the library tanh; |a| > 20 rounds to +-1 in double
+template <bool ACCURATE = false>
 __device__ inline double l_tanh_run(double phi, double invT)
 {
     const double a = phi * invT;

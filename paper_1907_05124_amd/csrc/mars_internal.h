@@ -53,6 +53,7 @@ struct DevBuf {
 struct Workspace {
     DevBuf Ma, Mb;          // dense state ping-pong buffers [Np x ldm]
     DevBuf invT;            // per-level per-run inverse temperatures
+    DevBuf invT64;          // the same in fp64 (dense fp32 form)
     DevBuf T0;              // [R] double
     DevBuf nlev;            // [R] int32 levels in range per run
     DevBuf runstat;         // [R x 4] int64: sweeps, levels, cap hits, spare
@@ -129,6 +130,7 @@ struct Instance {
     hipEvent_t done_event = nullptr;
     bool done_recorded = false;
     bool in_batch = false;  // owned by a batch until its member finishes
+    double tick_s = 0.0;    // seconds per tick of the device's constant-rate clock
     Workspace ws;
     std::mutex mu;
 };
@@ -151,8 +153,19 @@ void launch_init_T0(uint64_t seed, int R, double T_lo, double T_hi, const double
                     hipStream_t s);
 void launch_level_table(const mars_schedule &sc, int R, const double *T0, int kmax, int ldt, float *invT32,
                         double *invT64, int32_t *nlev, hipStream_t s);
+// The device result area of a solve: mars_result, then the device clock at
+// the start of the solve (uint64, written by launch_stamp), then the best run
+// index (int32 at +16).
+__host__ __device__ inline uint64_t *result_stamp(mars_result *res_dev) { return reinterpret_cast<uint64_t *>(res_dev + 1); }
+inline int32_t *result_best(mars_result *res_dev)
+{
+    return reinterpret_cast<int32_t *>(reinterpret_cast<char *>(res_dev + 1) + 16);
+}
+void launch_stamp(uint64_t *slot, hipStream_t s);
+// best of runs into res_dev; res_dev->seconds = device clock now minus
+// *result_stamp(res_dev), times tick_s
 void launch_argmin(const double *E, const double *T0, const int64_t *runstat, int R, int N, double wsum,
-                   mars_result *res_dev, int32_t *best_dev, hipStream_t s);
+                   mars_result *res_dev, int32_t *best_dev, double tick_s, hipStream_t s);
 void launch_gather_best(const int8_t *spins, int ld, const int32_t *best_dev, int N, int8_t *out, hipStream_t s);
 void launch_graph_energy(const Instance &I, const int8_t *spins, int R, double *E, hipStream_t s);
 // dense exact energy on the int8 matrix cores (k_energy.hip)
@@ -169,17 +182,22 @@ void launch_dense_init_state(uint64_t seed, int N, int R, int ldm, const float *
 constexpr int SEQ_NB = 64;
 void launch_dense_seq_block(const Instance &I, const float *Mold, float *Mnew, float *phi, int ldm, int R, int p0,
                             int p1, const float *invT, float gamma, uint32_t *dmax, hipStream_t s);
+// invT64 (or null): fp64 1/T of the runs, then the update is evaluated in fp64
 void launch_dense_phase_f32(const Instance &I, const float *Mold, float *Mnew, int ldm, int R, int p0, int p1,
-                            const float *invT, float gamma, uint32_t *dmax, hipStream_t s);
+                            const float *invT, const double *invT64, float gamma, uint32_t *dmax, hipStream_t s);
 void launch_dense_round(const float *M, int ldm, int N, int R, int Ke, int8_t *spad, int8_t *spins, float *m_final,
                         hipStream_t s);
 void launch_dense_runstat(int R, const int32_t *nlev, int64_t *runstat, hipStream_t s);
 void launch_dense_fixpoint(const Instance &I, hipStream_t s);
-void launch_dense_advance_init(int R, const float *table, const int32_t *nlev, float *invT_cur, int32_t *state,
-                               int64_t *runstat, uint32_t *dmax, hipStream_t s);
-void launch_dense_advance(int R, const float *table, int ldt, const int32_t *nlev, int max_sweeps, double d_min,
-                          float *invT_cur, int32_t *state, int64_t *runstat, uint32_t *dmax, uint32_t *active,
-                          hipStream_t s);
+// table64 / invT64_cur: the fp64 copies (both null when the form has none)
+void launch_dense_advance_init(int R, const float *table, const double *table64, const int32_t *nlev,
+                               float *invT_cur, double *invT64_cur, int32_t *state, int64_t *runstat, uint32_t *dmax,
+                               hipStream_t s);
+void launch_dense_advance(int R, const float *table, const double *table64, int ldt, const int32_t *nlev,
+                          int max_sweeps, double d_min, float *invT_cur, double *invT64_cur, int32_t *state,
+                          int64_t *runstat, uint32_t *dmax, uint32_t *active, int32_t *spl, int cap, hipStream_t s);
+// one sweep per level: spl[r * cap + k] = (k < nlev[r])
+void launch_dense_spl_ones(int R, const int32_t *nlev, int32_t *spl, int cap, hipStream_t s);
 
 // dense, bf16 form (k_dense_bf16.hip)
 mars_status ensure_bf16_couplings(Instance &I, hipStream_t s);
@@ -220,6 +238,7 @@ struct DenseRun {
     float gamma = 1.0f;
     double *T0 = nullptr;
     float *table = nullptr;  // [kmax x ldt] 1/T per level and run, -1 past a run's levels
+    double *table64 = nullptr;  // the same in fp64 (fp32 form; null for bf16 and sequential)
     int32_t *nlev = nullptr;
     void *Ma = nullptr, *Mb = nullptr;  // state ping-pong buffers (Ma holds the initial state)
 };
@@ -239,6 +258,8 @@ struct GraphSolve {
     int8_t *spins;
     double *energies;
     int64_t *runstat;      // [R x 4]
+    int32_t *spl = nullptr;  // [R x spl_cap] sweeps per visited level (zero filled), or null
+    int spl_cap = 0;
 };
 mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s);
 
@@ -278,6 +299,8 @@ struct GraphArgs {
     void *m_final;
     int8_t *spins;
     int64_t *runstat;
+    int32_t *spl;  // [R x spl_cap] sweeps per visited level, or null
+    int spl_cap;
 };
 
 hipError_t launch_lattice_solve(const GraphArgs &a, int esz, int rpw, bool jac, bool trackd, hipStream_t s);

@@ -94,8 +94,9 @@ static void destroy_instance(Instance *I)
         if (p)
             (void)hipFree(p);
     Workspace &w = I->ws;
-    DevBuf *bufs[] = {&w.Ma, &w.Mb, &w.invT, &w.T0, &w.nlev, &w.runstat, &w.dmax, &w.spins, &w.spad,
-                      &w.energies, &w.partial, &w.result, &w.runstate, &w.flag};
+    DevBuf *bufs[] = {&w.Ma,      &w.Mb,       &w.invT,   &w.invT64, &w.T0,       &w.nlev, &w.runstat,
+                      &w.dmax,    &w.spins,    &w.spad,   &w.energies, &w.partial, &w.result, &w.runstate,
+                      &w.flag,    &w.spec,     &w.phi};
     for (DevBuf *b : bufs)
         free_buf(*b);
     if (I->own_stream)
@@ -175,6 +176,12 @@ static mars_status start_instance(Instance *I)
     e = hipEventCreateWithFlags(&I->done_event, hipEventDisableTiming);
     if (e != hipSuccess)
         return hip_error(e, "hipEventCreate");
+    int khz = 0;
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess || khz <= 0)
+        return e != hipSuccess ? hip_error(e, "hipDeviceGetAttribute(WallClockRate)")
+                               : set_error(MARS_E_DEVICE, "device reports no constant-rate clock");
+    I->tick_s = 1.0 / (1000.0 * (double)khz);
     return MARS_OK;
 }
 
@@ -720,7 +727,8 @@ mars_status dense_setup(Instance *I, int R, const mars_schedule &sc, uint64_t se
         d.bf16 ? sizeof(unsigned short) * (size_t)d.ldr * I->Np : sizeof(float) * (size_t)I->Np * d.ldm;
     if ((st = ensure(w.Ma, mbytes)) || (st = ensure(w.Mb, mbytes)) || (st = ensure(w.T0, sizeof(double) * R)) ||
         (st = ensure(w.nlev, sizeof(int32_t) * R)) || (st = ensure(w.runstat, sizeof(int64_t) * 4 * R)) ||
-        (st = ensure(w.dmax, sizeof(uint32_t) * d.ldr)) || (st = ensure(w.runstate, sizeof(int32_t) * 4 * d.ldr)) ||
+        (st = ensure(w.dmax, sizeof(uint32_t) * d.ldr)) ||
+        (st = ensure(w.runstate, (sizeof(int32_t) * 4 + sizeof(double)) * d.ldr)) ||
         (st = ensure(w.flag, 64)))
         return st;
     launch_fill_u32((uint32_t *)w.Ma.p, 0u, mbytes / 4, s);
@@ -744,7 +752,13 @@ mars_status dense_setup(Instance *I, int R, const mars_schedule &sc, uint64_t se
     d.ldt = d.ldr;
     d.table = (float *)w.invT.p;
     d.nlev = (int32_t *)w.nlev.p;
-    launch_level_table(sc, R, d.T0, d.kmax, d.ldt, d.table, nullptr, d.nlev, s);
+    // the fp32 form evaluates its update in fp64 and keeps an fp64 copy of the table
+    if (!d.bf16 && sc.update != MARS_SEQUENTIAL) {
+        if ((st = ensure(w.invT64, sizeof(double) * (size_t)std::max(d.kmax, 1) * d.ldr)) != MARS_OK)
+            return st;
+        d.table64 = (double *)w.invT64.p;
+    }
+    launch_level_table(sc, R, d.T0, d.kmax, d.ldt, d.table, d.table64, d.nlev, s);
     if (d.bf16)
         launch_bf16_init_state(seed, N, R, I->Np, m0, (unsigned short *)w.Ma.p, s);
     else
@@ -783,7 +797,7 @@ mars_status dense_finish(Instance *I, const DenseRun &d, const void *cur, float 
     else
         launch_dense_round((const float *)cur, d.ldm, N, R, I->Ke, spad, spins, m_final, s);
     launch_dense_energy_i8(*I, spad, R, E, I->ws.partial.p, s);
-    launch_argmin(E, d.T0, (const int64_t *)w.runstat.p, R, N, I->wsum, res_dev, best_dev, s);
+    launch_argmin(E, d.T0, (const int64_t *)w.runstat.p, R, N, I->wsum, res_dev, best_dev, I->tick_s, s);
     if (best_spins)
         launch_gather_best(spad, I->Ke, best_dev, N, best_spins, s);
     MARS_HIP(hipGetLastError());
@@ -792,7 +806,7 @@ mars_status dense_finish(Instance *I, const DenseRun &d, const void *cur, float 
 
 static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const float *m0,
                                const double *T0in, float *m_final, int8_t *spins, double *E, int8_t *best_spins,
-                               mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+                               int32_t *spl, int spl_cap, mars_result *res_dev, int32_t *best_dev, hipStream_t s)
 {
     DenseRun d;
     mars_status st = dense_setup(I, R, sc, seed, m0, T0in, d, s);
@@ -818,7 +832,7 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
             return st;
         phi = (float *)w.phi.p;
     }
-    auto sweep = [&](const float *invT, uint32_t *dmax) {
+    auto sweep = [&](const float *invT, const double *invT64, uint32_t *dmax) {
         for (int b = 0; b < B; ++b) {
             if (pb[b + 1] <= pb[b])
                 continue;
@@ -829,32 +843,36 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
                 launch_dense_phase_bf16(*I, (const unsigned short *)cur, (unsigned short *)nxt, I->Np, R, pb[b],
                                         pb[b + 1], invT, gamma, dmax, variant, s);
             else
-                launch_dense_phase_f32(*I, (const float *)cur, (float *)nxt, ldm, R, pb[b], pb[b + 1], invT, gamma,
-                                       dmax, s);
+                launch_dense_phase_f32(*I, (const float *)cur, (float *)nxt, ldm, R, pb[b], pb[b + 1], invT, invT64,
+                                       gamma, dmax, s);
         }
         std::swap(cur, nxt);
     };
     int64_t *runstat = (int64_t *)w.runstat.p;
     if (sc.max_sweeps == 1) {
         for (int k = 0; k < kmax; ++k)
-            sweep(table + (size_t)k * ldt, nullptr);
+            sweep(table + (size_t)k * ldt, d.table64 ? d.table64 + (size_t)k * ldt : nullptr, nullptr);
         launch_dense_runstat(R, nlev, runstat, s);
+        if (spl)
+            launch_dense_spl_ones(R, nlev, spl, spl_cap, s);
     } else {
         // several sweeps per level: per-run level state advanced on the device
-        float *invT_cur = (float *)w.runstate.p;  // [ldr] floats followed by [ldr x 2] ints
+        // [ldr] floats, [ldr x 2] ints, then [ldr] doubles
+        float *invT_cur = (float *)w.runstate.p;
         int32_t *state = (int32_t *)(invT_cur + ldr);
+        double *invT64_cur = d.table64 ? (double *)(state + 2 * (size_t)ldr) : nullptr;
         uint32_t *dmax = (uint32_t *)w.dmax.p;
         uint32_t *active = (uint32_t *)w.flag.p;
-        launch_dense_advance_init(R, table, nlev, invT_cur, state, runstat, dmax, s);
+        launch_dense_advance_init(R, table, d.table64, nlev, invT_cur, invT64_cur, state, runstat, dmax, s);
         const long long cap = (long long)kmax * sc.max_sweeps + 1;
         long long done_sweeps = 0;
         const int chunk = 8;
         while (done_sweeps < cap) {
             for (int c = 0; c < chunk; ++c) {
-                sweep(invT_cur, dmax);
+                sweep(invT_cur, invT64_cur, dmax);
                 launch_fill_u32(active, 0u, 1, s);
-                launch_dense_advance(R, table, ldt, nlev, sc.max_sweeps, sc.d_min, invT_cur, state, runstat, dmax,
-                                     active, s);
+                launch_dense_advance(R, table, d.table64, ldt, nlev, sc.max_sweeps, sc.d_min, invT_cur, invT64_cur,
+                                     state, runstat, dmax, active, spl, spl_cap, s);
                 ++done_sweeps;
             }
             uint32_t h_active = 0;
@@ -869,7 +887,7 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
 
 static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const void *m0,
                                const double *T0in, void *m_final, int8_t *spins, double *E, int8_t *best_spins,
-                               mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+                               int32_t *spl, int spl_cap, mars_result *res_dev, int32_t *best_dev, hipStream_t s)
 {
     Workspace &w = I->ws;
     mars_status st;
@@ -887,10 +905,12 @@ static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint
     g.spins = spins;
     g.energies = E;
     g.runstat = (int64_t *)w.runstat.p;
+    g.spl = spl;
+    g.spl_cap = spl_cap;
     if ((st = launch_graph_solve(*I, g, s)) != MARS_OK)
         return st;
     launch_graph_energy(*I, spins, R, E, s);
-    launch_argmin(E, T0, g.runstat, R, I->N, I->wsum, res_dev, best_dev, s);
+    launch_argmin(E, T0, g.runstat, R, I->N, I->wsum, res_dev, best_dev, I->tick_s, s);
     if (best_spins)
         launch_gather_best(spins, I->N, best_dev, I->N, best_spins, s);
     MARS_HIP(hipGetLastError());
@@ -915,12 +935,16 @@ static mars_status order_end(Instance *I, hipStream_t s)
 
 static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, uint64_t seed, const void *m0,
                               const double *T0, void *m_final, int8_t *spins, double *E, int8_t *best_spins,
-                              mars_result *res, hipStream_t s)
+                              int32_t *spl, int spl_cap, mars_result *res, hipStream_t s)
 {
     if (R < 1)
         return set_error(MARS_E_ARG, "runs must be >= 1");
     if (R >= (1 << 30))
         return set_error(MARS_E_ARG, "runs must be < 2^30");
+    if (spl && spl_cap < 1)
+        return set_error(MARS_E_ARG, "sweeps_per_level needs level_cap >= 1");
+    if (!spl)
+        spl_cap = 0;
     mars_status st = check_schedule(sched, I->kind);
     if (st != MARS_OK)
         return st;
@@ -945,12 +969,16 @@ static mars_status solve_impl(Instance *I, int R, const mars_schedule *sched, ui
     if (I->kind == KIND_DENSE && (st = ensure(w.partial, dense_energy_partial_bytes(*I, R))) != MARS_OK)
         return st;
     mars_result *res_dev = (mars_result *)w.result.p;
-    int32_t *best_dev = (int32_t *)((char *)w.result.p + sizeof(mars_result) + 16);
+    int32_t *best_dev = result_best(res_dev);
+    launch_stamp(result_stamp(res_dev), s);
+    if (spl)
+        launch_fill_u32(reinterpret_cast<uint32_t *>(spl), 0u, (size_t)R * spl_cap, s);
     if (I->kind == KIND_DENSE)
-        st = solve_dense(I, R, *sched, seed, (const float *)m0, T0, (float *)m_final, spins, E, best_spins, res_dev,
-                         best_dev, s);
+        st = solve_dense(I, R, *sched, seed, (const float *)m0, T0, (float *)m_final, spins, E, best_spins, spl,
+                         spl_cap, res_dev, best_dev, s);
     else
-        st = solve_graph(I, R, *sched, seed, m0, T0, m_final, spins, E, best_spins, res_dev, best_dev, s);
+        st = solve_graph(I, R, *sched, seed, m0, T0, m_final, spins, E, best_spins, spl, spl_cap, res_dev, best_dev,
+                         s);
     if (st != MARS_OK)
         return st;
     if ((st = order_end(I, s)) != MARS_OK)
@@ -1068,7 +1096,8 @@ static mars_status batch_add(Batch &b, Instance *I, int R, const mars_schedule *
         return fail(st);
     m.E = (double *)w.energies.p;
     m.res_dev = (mars_result *)w.result.p;
-    m.best_dev = (int32_t *)((char *)w.result.p + sizeof(mars_result) + 16);
+    m.best_dev = result_best(m.res_dev);
+    launch_stamp(result_stamp(m.res_dev), b.s);
     if ((st = dense_setup(I, R, *sc, seed, nullptr, nullptr, m.d, b.s)) != MARS_OK)
         return fail(st);
     for (int q = 0; q < kMaxBatchMembers; ++q)
@@ -1285,7 +1314,8 @@ mars_status mars_describe(const mars_instance *inst, const mars_schedule *sched,
 
 mars_status mars_solve_ex(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
                           const void *m0, const double *T0, double *T0_used, void *m_final, int8_t *spins,
-                          double *energies, int8_t *best_spins, mars_result *res, void *stream)
+                          double *energies, int8_t *best_spins, int32_t *sweeps_per_level, int32_t level_cap,
+                          mars_result *res, void *stream)
 {
     if (!inst)
         return set_error(MARS_E_ARG, "instance is NULL");
@@ -1295,7 +1325,7 @@ mars_status mars_solve_ex(mars_instance *inst, int32_t runs, const mars_schedule
         return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     mars_status st = solve_impl(I, runs, sched, seed, m0, T0, m_final, spins, energies, best_spins,
-                                T0_used ? nullptr : res, s);
+                                sweeps_per_level, level_cap, T0_used ? nullptr : res, s);
     if (st != MARS_OK || !T0_used)
         return st;
     MARS_HIP(hipMemcpyAsync(T0_used, I->ws.T0.p, sizeof(double) * runs, hipMemcpyDeviceToDevice, s));
@@ -1319,7 +1349,8 @@ mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_sched
     if (I->in_batch)
         return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    mars_status st = solve_impl(I, runs, sched, seed, m0, T0, m_final, spins, energies, best_spins, nullptr, s);
+    mars_status st =
+        solve_impl(I, runs, sched, seed, m0, T0, m_final, spins, energies, best_spins, nullptr, 0, nullptr, s);
     if (st != MARS_OK || !res_pinned)
         return st;
     MARS_HIP(hipMemcpyAsync(res_pinned, I->ws.result.p, sizeof(mars_result), hipMemcpyDeviceToHost, s));
@@ -1355,7 +1386,7 @@ mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *s
         }
     }
     mars_result tmp;
-    st = solve_impl(I, runs, sched, seed, nullptr, nullptr, nullptr, nullptr, dE, dbest, &tmp, s);
+    st = solve_impl(I, runs, sched, seed, nullptr, nullptr, nullptr, nullptr, dE, dbest, nullptr, 0, &tmp, s);
     if (st == MARS_OK) {
         hipError_t e = hipSuccess;
         if (best_spins && e == hipSuccess)

@@ -45,7 +45,7 @@ class Result(C.Structure):
     _fields_ = [("best_energy", C.c_double), ("best_cut", C.c_double), ("mean_energy", C.c_double),
                 ("best_T0", C.c_double), ("best_run", C.c_int32), ("runs", C.c_int32), ("hit_count", C.c_int64),
                 ("sweeps_executed", C.c_int64), ("spin_updates", C.c_int64), ("cap_hits", C.c_int64),
-                ("levels_executed", C.c_int64)]
+                ("levels_executed", C.c_int64), ("seconds", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,7 +77,7 @@ def load(path: str = LIB_PATH):
         L.mars_destroy.restype = None
         L.mars_describe.argtypes = [vp, C.POINTER(Schedule), C.POINTER(i32), C.POINTER(i32)]
         L.mars_solve.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, C.POINTER(Result)]
-        L.mars_solve_ex.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp,
+        L.mars_solve_ex.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp, i32,
                                     C.POINTER(Result), vp]
         L.mars_solve_async.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mars_energy.argtypes = [vp, vp, i32, vp, vp]
@@ -209,11 +209,14 @@ class Instance:
         return best, E, res.as_dict()
 
     def solve_ex(self, runs: int, schedule, seed: int, *, m0=None, T0=None, want_T0=False, want_m=False,
-                 want_spins=False, want_energies=True, want_best=True, sync=True, stream=None) -> dict:
+                 want_spins=False, want_energies=True, want_best=True, levels_cap: int = 0, sync=True,
+                 stream=None) -> dict:
         """Device outputs as torch tensors on the current device and stream.
 
         ``m0`` ([N, runs], float32, or float64 for fp64 schedules) and ``T0``
-        ([runs] float64) are device tensors or None."""
+        ([runs] float64) are device tensors or None.  ``levels_cap`` > 0 adds
+        ``sweeps_per_level`` ([runs, levels_cap] int32): the sweeps each run
+        ran at each level it visited."""
         import torch
 
         dev = torch.device("cuda", torch.cuda.current_device())
@@ -229,6 +232,8 @@ class Instance:
             out["energies"] = torch.empty(runs, dtype=torch.float64, device=dev)
         if want_best:
             out["best_spins"] = torch.empty(self.N, dtype=torch.int8, device=dev)
+        if levels_cap > 0:
+            out["sweeps_per_level"] = torch.empty((runs, levels_cap), dtype=torch.int32, device=dev)
         for name, t, dt in (("m0", m0, mdt), ("T0", T0, torch.float64)):
             if t is not None:
                 if t.device.type != "cuda" or t.dtype != dt or not t.is_contiguous():
@@ -240,6 +245,7 @@ class Instance:
         _check(load().mars_solve_ex(self._h, int(runs), C.byref(s), seed & (2**64 - 1), _ptr(m0), _ptr(T0),
                                     _ptr(out.get("T0")), _ptr(out.get("m")), _ptr(out.get("spins")),
                                     _ptr(out.get("energies")), _ptr(out.get("best_spins")),
+                                    _ptr(out.get("sweeps_per_level")), int(max(levels_cap, 0)),
                                     C.byref(res) if sync else None, C.c_void_p(stream.cuda_stream)))
         if sync:
             out["result"] = res.as_dict()

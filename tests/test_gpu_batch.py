@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1907_05124_amd import inputs as I
-from tests.gpu_common import announce, require_gpu
+from tests.gpu_common import announce, require_gpu, solve_summary
 
 pytestmark = pytest.mark.gpu
 
@@ -84,7 +84,7 @@ def test_batch_equals_alone(graph, monkeypatch):
     assert sorted(finished) == list(range(len(cases)))
     for i, (a, h) in enumerate(zip(alone, handles)):
         res = M.Instance.read_result(bufs[i])
-        assert res == a["result"], (i, res, a["result"])
+        assert solve_summary(res) == solve_summary(a["result"]), (i, res, a["result"])
         assert np.array_equal(outs[i]["best_spins"].cpu().numpy(), a["best_spins"].cpu().numpy()), i
         h.close()
 
@@ -143,7 +143,7 @@ def test_batch_full_and_refusals(graph, monkeypatch):
     # released: the instances solve alone again, with the batch's results
     for t in range(4):
         r_alone = handles[t].solve_ex(64, sch, 100 + t)["result"]
-        assert r_alone == M.Instance.read_result(bufs[t])
+        assert solve_summary(r_alone) == solve_summary(M.Instance.read_result(bufs[t]))
     for h in handles:
         h.close()
 

@@ -9,7 +9,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1907_05124_amd import inputs as I
-from tests.gpu_common import announce, check_trajectory, require_gpu
+from tests.gpu_common import announce, c16_parity, check_replay, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -92,18 +92,25 @@ def test_one_level_parity(case, precision, tol):
 @pytest.mark.parametrize("update", ["phased", "jacobi"])
 def test_damped_parity(case, update):
     """Damped update m <- (1 - g) m + g tanh(...) with g = 0.5 (the damped
-    kernels are separate instantiations): five fp32 levels within 1e-5 of the
-    oracle."""
+    kernels are separate instantiations): after one fp32 level every element
+    within 1e-5 of the oracle; after five, every run the oracle finds well
+    conditioned (as in test_anneal_parity, at most 5 % excluded)."""
     M = _mars()
     inst = CASES[case]()
-    sch = _rel_sched(inst, precision="fp32", update=update, damping=0.5, level_count=5)
     R = 200
     announce("graph damped", case, update, R)
-    with M.Instance.from_inputs(inst) as g:
-        out = g.solve_ex(R, sch, 29, want_m=True)
-    ref = O.solve(inst, R, sch, 29, run_count=R)
-    err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
-    assert err <= 1e-5, err
+    for levels in (1, 5):
+        sch = _rel_sched(inst, precision="fp32", update=update, damping=0.5, level_count=levels)
+        with M.Instance.from_inputs(inst) as g:
+            out = g.solve_ex(R, sch, 29, want_m=True)
+        ref = O.solve(inst, R, sch, 29, run_count=R)
+        m = out["m"].cpu().numpy()
+        if levels == 1:
+            err = np.max(np.abs(m.astype(np.float64) - ref["m"]))
+            assert err <= 1e-5, err
+        else:
+            c16_parity(m, inst, R, sch, 29, ref, "fp32", max_excluded=0.05,
+                       label="%s damped %s level 5" % (case, update))
 
 
 RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "er_dense_isolated", "er_int8", "er_int8_dense", "ea3d_8",
@@ -218,31 +225,49 @@ def test_one_level_fp16_storage(case, R):
     assert np.all(err <= tol), float(np.max(err / tol))
 
 
-@pytest.mark.parametrize("case", ["ea2d_16", "ea3d_8", "er_pm1", "lat_field"])
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-9)])
-def test_anneal_parity(case, precision, tol):
-    """Full 300-level anneal on the oracle's well-conditioned runs; energies of
-    equal spin vectors equal."""
+def _decided_spins_agree(S, m, ref, bar):
+    """Spins equal the oracle's wherever the oracle's |m| exceeds the bar on
+    runs that meet it (elsewhere the sign is a rounding decision)."""
+    close = np.max(np.abs(np.asarray(m, dtype=np.float64) - ref["m"]), axis=0) <= bar
+    decided = np.abs(ref["m"]) > bar
+    assert not np.any((S.T != ref["spins"].T) & decided & close[None, :])
+
+
+@pytest.mark.parametrize("case", ["ea2d_16", "ea3d_8", "er_pm1", "lat_field", "er_field"])
+@pytest.mark.parametrize("precision,levels", [("fp64", 10), ("fp64", 300), ("fp32", 300)])
+def test_anneal_parity(case, precision, levels):
+    """Geometric anneal checked at levels 10 and 300 (fp64) and at the end
+    (fp32): every run the oracle finds well conditioned (final m moves by
+    <= 1e-6 under a 1e-9 change of m0; fp32: and by <= 2.5e-6 when T0 moves
+    by one fp32 ulp) agrees within 1e-9 (fp64) / 1e-5 (fp32) in every
+    element, at most 5 % of the runs excluded; decided spins agree and
+    energies of equal spin vectors are equal.  (Mid-anneal, the fp32 form's
+    rounding at every sweep moves some runs by more than 1e-5 in ways a
+    single change of the oracle's inputs does not predict; the fp32 form is
+    held to the bar after one level and at the end.)"""
     M = _mars()
     inst = CASES[case]()
-    sch = _rel_sched(inst, precision=precision)
+    sch = _rel_sched(inst, precision=precision, level_count=levels)
     R = 96
-    announce("graph anneal", case, precision, R)
+    announce("graph anneal", case, precision, levels, R)
     with M.Instance.from_inputs(inst) as g:
         out = g.solve_ex(R, sch, 23, want_m=True, want_spins=True)
     ref = O.solve(inst, R, sch, 23, run_count=R)
     S = out["spins"].cpu().numpy()
     E = out["energies"].cpu().numpy()
-    within = check_trajectory(out["m"].cpu().numpy(), inst, R, sch, 23, ref, precision, spins=S)
-    print("runs within the base bar: %.2f" % within)
-    assert within >= 0.5
+    m = out["m"].cpu().numpy()
+    bar = 1e-5 if precision == "fp32" else 1e-9
+    c16_parity(m, inst, R, sch, 23, ref, precision, max_excluded=0.05,
+               label="%s %s level %d" % (case, precision, levels))
+    _decided_spins_agree(S, m, ref, bar)
     same = np.all(S == ref["spins"], axis=1)
-    print("runs with identical spins: %.2f" % same.mean())
     assert np.array_equal(E[same], ref["energy"][same])
 
 
 def test_config1_lattice_fp64_full():
-    """2D +-J L=16, 1024 runs, T0 ~ U[0.5, 3], 300 geometric levels to 0.02, fp64."""
+    """2D +-J L=16, 1024 runs, T0 ~ U[0.5, 3], 300 geometric levels to 0.02,
+    fp64: every well-conditioned run within 1e-9 of the oracle (at most 2 %
+    excluded), decided spins equal, energies of equal spins equal."""
     M = _mars()
     w = I.workload("ea2d_L16", seed=1)
     announce("config1 fp64", w.runs)
@@ -250,11 +275,11 @@ def test_config1_lattice_fp64_full():
         out = g.solve_ex(w.runs, w.schedule, 1, want_m=True, want_spins=True)
     ref = O.solve(w.instance, w.runs, w.schedule, 1, run_count=w.runs)
     S = out["spins"].cpu().numpy()
-    within = check_trajectory(out["m"].cpu().numpy(), w.instance, w.runs, w.schedule, 1, ref, "fp64", spins=S)
-    assert within >= 0.9
+    m = out["m"].cpu().numpy()
+    c16_parity(m, w.instance, w.runs, w.schedule, 1, ref, "fp64", max_excluded=0.02, label="config 1 fp64")
+    _decided_spins_agree(S, m, ref, 1e-9)
     E = out["energies"].cpu().numpy()
     same = np.all(S == ref["spins"], axis=1)
-    assert same.mean() >= 0.95
     assert np.array_equal(E[same], ref["energy"][same])
     assert out["result"]["best_energy"] == E.min()
 
@@ -310,47 +335,96 @@ def test_jacobi_sublattice_symmetry_gpu():
             assert np.array_equal(b["m"].cpu().numpy(), ((-1.0) ** k) * D[:, None] * a["m"].cpu().numpy())
 
 
-@pytest.mark.parametrize("R", [64, 1024])
-def test_paper_schedule_graph(R):
-    """Linear scheduler with d < d_min = 1e-4 on a sparse graph: identical level
-    counts, near-identical sweep totals and final states (R = 1024 puts two
-    runs in each workgroup and thread)."""
+PAPER_CASES = {
+    "er400": (lambda: I.er_instance(400, 10, p=0.03, weights="pm1"), 2.0, 0.2),
+    "er_field": (lambda: CASES["er_field"](), 2.0, 0.2),
+    "ea2d_16": (lambda: CASES["ea2d_16"](), 1.5, 0.1),
+    "ea3d_8": (lambda: CASES["ea3d_8"](), 1.5, 0.1),
+}
+
+
+@pytest.mark.parametrize("case", sorted(PAPER_CASES))
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("R", [64, 2048])
+def test_paper_schedule_replay(case, precision, R):
+    """The paper's scheduler (linear decrement, sweeps until d < d_min = 1e-4)
+    by replay: the oracle runs the GPU's per-level sweep counts on 32 runs
+    spread over the range and agrees within 1e-5 (fp32) / 1e-9 (fp64) on
+    every well-conditioned run; a stop decision that differs has its oracle d
+    within 1e-5 of d_min.  R = 2048 puts several runs in each workgroup, and
+    up to four in each thread of the sparse solver, so that runs of one
+    workgroup finish their levels at different sweeps."""
     M = _mars()
-    inst = I.er_instance(400, 10, p=0.03, weights="pm1")
+    make, hi, step = PAPER_CASES[case]
+    inst = make()
     s = I.field_scale(inst)
-    sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=2.0 * s, c_step=0.2 * s, max_sweeps=400, d_min=1e-4)
-    announce("graph paper schedule", R)
+    sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=hi * s, c_step=step * s, max_sweeps=1000, d_min=1e-4,
+                     precision=precision)
+    cap = 64
+    announce("graph paper schedule replay", case, precision, R)
     with M.Instance.from_inputs(inst) as g:
-        out = g.solve_ex(R, sch, 41, want_m=True)
-    ref = O.solve(inst, R, sch, 41, run_count=R)
+        out = g.solve_ex(R, sch, 41, want_m=True, levels_cap=cap)
+    spl = out["sweeps_per_level"].cpu().numpy()
     res = out["result"]
-    assert res["levels_executed"] == int(ref["levels"].sum())
-    assert abs(res["sweeps_executed"] - int(ref["sweeps"].sum())) <= 0.02 * ref["sweeps"].sum()
-    m = out["m"].cpu().numpy().astype(np.float64)
-    assert (np.max(np.abs(m - ref["m"]), axis=0) <= 1e-3).mean() >= 0.9
+    assert res["sweeps_executed"] == int(spl.sum())
+    sample = list(range(0, R, max(1, R // 32)))[:32]
+    check_replay(out["m"].cpu().numpy(), spl, inst, R, sch, 41, precision, sample,
+                 label="%s %s R=%d" % (case, precision, R))
 
 
 @pytest.mark.parametrize("name", ["er800", "er20000", "ea3d_L32"])
 def test_full_size_sampled(name):
-    """Paper-shaped sizes in the launch configuration used for them: sampled runs
-    match the oracle (fp32/fp16 forms: best energy gap and spin agreement)."""
+    """Paper-shaped sizes in the benchmark's launch configuration (all runs on
+    the GPU), fp32 form: 32 sampled runs' final magnetisations within 1e-5 of
+    the oracle's in every element of every well-conditioned run (at most 5 %
+    excluded), decided spins equal and energies of equal spins equal."""
     M = _mars()
     w = I.workload(name, seed=1)
     R = w.runs
+    sch = w.schedule.replace(precision="fp32")
     announce("graph full size", name, R)
+    with M.Instance.from_inputs(w.instance) as g:
+        out = g.solve_ex(R, sch, 1, want_m=True, want_spins=True)
+    m = out["m"].cpu().numpy()
+    S = out["spins"].cpu().numpy()
+    E = out["energies"].cpu().numpy()
+    excl = 0.0
+    for r0 in (0, R // 3, R // 2 + 5, R - 8):
+        ref = O.solve(w.instance, R, sch, 1, run_begin=r0, run_count=8)
+        excl += c16_parity(m[:, r0:r0 + 8], w.instance, R, sch, 1, ref, "fp32", run_begin=r0, max_excluded=1.0,
+                           label="%s fp32 runs %d..%d" % (name, r0, r0 + 7))
+        _decided_spins_agree(S[r0:r0 + 8], m[:, r0:r0 + 8], ref, 1e-5)
+        for q in range(8):
+            if np.array_equal(S[r0 + q], ref["spins"][q]):
+                assert E[r0 + q] == ref["energy"][q]
+    assert excl / 4 <= 0.05
+    assert out["result"]["best_energy"] == E.min()
+
+
+@pytest.mark.parametrize("name", ["er20000", "ea3d_L32"])
+def test_full_size_fp16_storage(name):
+    """The fp16-storage form at full size (the benchmark's form): no
+    elementwise bar (every stored value is rounded to fp16); on 32 sampled
+    runs the fraction of rounded spins that differ from the FP64 oracle's (up
+    to a global flip) stays below 2 % and the sample's best energy is within
+    0.5 % of the oracle's."""
+    M = _mars()
+    w = I.workload(name, seed=1)
+    R = w.runs
+    announce("graph full size fp16", name, R)
     with M.Instance.from_inputs(w.instance) as g:
         out = g.solve_ex(R, w.schedule, 1, want_spins=True)
     S = out["spins"].cpu().numpy()
     E = out["energies"].cpu().numpy()
-    sample = [0, R // 3, R - 1]
-    fp16 = w.schedule.precision == "fp16"
-    agree = []
-    for r in sample:
-        one = O.solve(w.instance, R, w.schedule.replace(precision="fp64"), 1, run_begin=r, run_count=1)
-        agree.append(np.mean(S[r] == one["spins"][0]))
-        if np.array_equal(S[r], one["spins"][0]):
-            assert E[r] == one["energy"][0]
-        if fp16:
-            assert abs(E[r] - one["energy"][0]) <= 0.05 * abs(one["energy"][0])
-    assert np.mean(agree) >= (0.8 if fp16 else 0.9)
+    mism, Eg, Eo = [], [], []
+    for r0 in (0, R // 3, R // 2 + 5, R - 8):
+        ref = O.solve(w.instance, R, w.schedule.replace(precision="fp64"), 1, run_begin=r0, run_count=8)
+        d = np.mean(S[r0:r0 + 8] != ref["spins"], axis=1)
+        d = np.minimum(d, np.mean(S[r0:r0 + 8] != -ref["spins"], axis=1))
+        mism += d.tolist()
+        Eg += E[r0:r0 + 8].tolist()
+        Eo += ref["energy"].tolist()
+    gap = (min(Eg) - min(Eo)) / abs(min(Eo))
+    print("[fp16] %s: spin mismatch %.4f, best-energy gap %.2e" % (name, float(np.mean(mism)), gap), flush=True)
+    assert np.mean(mism) <= 0.02 and gap <= 5e-3
     assert out["result"]["best_energy"] == E.min()

@@ -4,7 +4,7 @@ and the solves really overlapped."""
 import numpy as np
 import pytest
 
-from tests.gpu_common import announce, require_gpu
+from tests.gpu_common import announce, require_gpu, solve_summary
 
 pytestmark = pytest.mark.gpu
 
@@ -30,5 +30,5 @@ def test_served_results_equal_alone(batching):
         assert c.rid == r.rid
         with M.Instance.from_inputs(r.instance) as g:
             alone = g.solve_ex(r.runs, r.schedule, r.seed, want_best=True)
-        assert alone["result"] == c.result, r.rid
+        assert solve_summary(alone["result"]) == solve_summary(c.result), r.rid
         assert np.array_equal(alone["best_spins"].cpu().numpy(), c.best_spins), r.rid
