@@ -215,6 +215,22 @@ mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_sched
  * the call returns after enqueueing.  Errors: MARS_E_ARG, MARS_E_DEVICE. */
 mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, double *energies, void *stream);
 
+/* mars_energy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same energies, bit for bit, with no hipMalloc, hipFree or other allocation
+ * on any call.  Dense instances work in a fixed scratch array of 32 MiB per
+ * device, part of the library's image (each device it runs on holds it until
+ * the process ends): R spin vectors of N spins need
+ * round_up(ceil(R/128)*128 * Ke, 256) + (Me/128) * R * 16 bytes, Ke = Me =
+ * round_up(N, 128) (N = 2000: up to about 14000 vectors); larger requests
+ * return MARS_E_UNSUPPORTED and write nothing.  Lattice and sparse
+ * instances need no scratch.  Every call on one device shares its array:
+ * calls whose stream work overlaps on one device race (calls on one
+ * instance are ordered by the library; on distinct instances order them on
+ * one stream).  Arguments, layouts, ownership and the other errors as
+ * mars_energy. */
+mars_status mars_energy_noalloc(mars_instance *inst, const int8_t *spins, int32_t R, double *energies, void *stream);
+
 /* Extreme eigenvalues of the couplings J (h is not involved), estimated by
  * `steps` Lanczos steps (capped at N) from a start vector drawn with `seed`,
  * in fp64 on the device.  They set the temperature scale of an anneal: the

@@ -7,7 +7,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -1427,6 +1429,82 @@ mars_status mars_energy(mars_instance *inst, const int8_t *spins, int32_t R, dou
             return st;
         launch_pad_spins(*I, spins, R, (int8_t *)I->ws.spad.p, s);
         launch_dense_energy_i8(*I, (const int8_t *)I->ws.spad.p, R, energies, I->ws.partial.p, s);
+    } else {
+        launch_graph_energy(*I, spins, R, energies, s);
+    }
+    MARS_HIP(hipGetLastError());
+    return order_end(I, s);
+}
+
+// ---------------------------------------------------------------------------
+// exact energies with no allocation: a fixed scratch array per device
+// ---------------------------------------------------------------------------
+
+// Scratch of mars_energy_noalloc (dense instances: the zero-padded run-major
+// spin operand, then the per-tile 128-bit partial sums).  Each device the
+// library runs on holds its own copy until the process ends.  In host code
+// this name is not a device address: only the pointer returned by
+// hipGetSymbolAddress for the current device is passed to kernels.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices];
+
+// Device address of `scratch` on device dev (which must be current), looked up
+// once per device.
+static mars_status scratch_on_device(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return set_error(MARS_E_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return set_error(MARS_E_DEVICE, "hipGetSymbolAddress(scratch) returned no address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MARS_OK;
+}
+
+mars_status mars_energy_noalloc(mars_instance *inst, const int8_t *spins, int32_t R, double *energies, void *stream)
+{
+    if (!inst || !spins || !energies || R < 1)
+        return set_error(MARS_E_ARG, "need instance, spins, energies and R >= 1");
+    Instance *I = reinterpret_cast<Instance *>(inst);
+    std::lock_guard<std::mutex> lk(I->mu);
+    if (I->in_batch)
+        return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
+    size_t spad_bytes = 0, part_bytes = 0;
+    if (I->kind == KIND_DENSE) {
+        spad_bytes = (dense_spin_operand_bytes(*I, R) + 255) & ~(size_t)255;
+        part_bytes = dense_energy_partial_bytes(*I, R);
+        if (spad_bytes + part_bytes > kNoAllocScratchBytes)
+            return set_error(MARS_E_UNSUPPORTED,
+                             "mars_energy_noalloc: " + std::to_string(R) + " spin vectors of N = " +
+                                 std::to_string(I->N) + " need " + std::to_string(spad_bytes + part_bytes) +
+                                 " bytes of scratch, more than its " + std::to_string(kNoAllocScratchBytes));
+    }
+    MARS_HIP(hipSetDevice(I->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    mars_status st = order_begin(I, s);
+    if (st != MARS_OK)
+        return st;
+    if (I->kind == KIND_DENSE) {
+        void *base = nullptr;
+        if ((st = scratch_on_device(I->device, &base)) != MARS_OK)
+            return st;
+        int8_t *spad = reinterpret_cast<int8_t *>(base);
+        void *partial = reinterpret_cast<unsigned char *>(base) + spad_bytes;
+        // every byte of both regions is written before it is read (padding
+        // included), so nothing needs clearing between calls
+        launch_pad_spins(*I, spins, R, spad, s);
+        launch_dense_energy_i8(*I, spad, R, energies, partial, s);
     } else {
         launch_graph_energy(*I, spins, R, energies, s);
     }

@@ -52,8 +52,8 @@ class Result(C.Structure):
 
 
 EXPORTS = ["mars_create", "mars_create_csr", "mars_create_lattice", "mars_destroy", "mars_describe", "mars_solve",
-           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_spectrum", "mars_auto_temperatures",
-           "mars_batch_create", "mars_batch_add", "mars_batch_step", "mars_batch_destroy", "mars_status_str",
+           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_energy_noalloc", "mars_spectrum",
+           "mars_auto_temperatures", "mars_batch_create", "mars_batch_add", "mars_batch_step", "mars_batch_destroy", "mars_status_str",
            "mars_last_error"]
 
 _lib = None
@@ -81,6 +81,7 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(Result), vp]
         L.mars_solve_async.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mars_energy.argtypes = [vp, vp, i32, vp, vp]
+        L.mars_energy_noalloc.argtypes = [vp, vp, i32, vp, vp]
         L.mars_spectrum.argtypes = [vp, i32, u64, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
         L.mars_auto_temperatures.argtypes = [vp, i32, u64, C.POINTER(Schedule), vp]
         L.mars_batch_create.argtypes = [vp, C.POINTER(vp)]
@@ -93,8 +94,8 @@ def load(path: str = LIB_PATH):
         L.mars_last_error.argtypes = []
         L.mars_last_error.restype = C.c_char_p
         for f in ("mars_create", "mars_create_csr", "mars_create_lattice", "mars_describe", "mars_solve",
-                  "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_spectrum", "mars_auto_temperatures",
-                  "mars_batch_create", "mars_batch_add", "mars_batch_step"):
+                  "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_energy_noalloc", "mars_spectrum",
+                  "mars_auto_temperatures", "mars_batch_create", "mars_batch_add", "mars_batch_step"):
             getattr(L, f).restype = C.c_int
         _lib = L
         return L
@@ -278,6 +279,20 @@ class Instance:
         """Decode a pinned result buffer filled by solve_async (after the stream passed it)."""
         raw = bytes(result_buf.cpu().numpy()[: C.sizeof(Result)])
         return Result.from_buffer_copy(raw).as_dict()
+
+    def energy_noalloc(self, spins, energies):
+        """mars_energy_noalloc: exact energies of device spins [R, N] int8 into
+        the caller's float64 [R] tensor, with no device allocation by the
+        library (current stream)."""
+        import torch
+
+        if spins.dtype != torch.int8 or spins.dim() != 2 or spins.shape[1] != self.N or not spins.is_contiguous():
+            raise ValueError("spins must be a contiguous int8 [R, N] CUDA tensor")
+        if energies.dtype != torch.float64 or energies.shape != (spins.shape[0],) or not energies.is_contiguous():
+            raise ValueError("energies must be a contiguous float64 [R] CUDA tensor")
+        _check(load().mars_energy_noalloc(self._h, _ptr(spins), int(spins.shape[0]), _ptr(energies),
+                                          C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        return energies
 
     def spectrum(self, steps: int = 100, seed: int = 1):
         """(lambda_min, lambda_max) of J by `steps` Lanczos steps on the device."""
