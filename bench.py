@@ -197,6 +197,38 @@ def work_roofline(done, requests, makespan_s):
             "frac": ideal / makespan_s if makespan_s > 0 else None}
 
 
+def served_cpu_baseline(base, seed_budget_s=12.0):
+    """The CPU oracle on a bounded sample of the served stream: requests in
+    stream order, each with as many runs as there are cores (full N and
+    schedule, fp64), skipping requests whose estimated cost would overrun the
+    budget; spin-updates/s over the sample."""
+    from oracle import oracle as O
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    t_tot, upd, n_req, n_runs = 0.0, 0, 0, 0
+    for r in base:
+        terms = r.N * r.N if r.dense else r.instance.nnz
+        est = terms * r.schedule.steps * cores / (cores * 4e8)  # ~4e8 coupling terms/s per core
+        if t_tot + est > seed_budget_s:
+            continue
+        n = min(cores, r.runs)
+        t0 = time.perf_counter()
+        res = O.solve(r.instance, r.runs, r.schedule.replace(precision="fp64"), r.seed, run_count=n, nthreads=cores)
+        t_tot += time.perf_counter() - t0
+        upd += int(res["sweeps"].sum()) * r.N
+        n_req += 1
+        n_runs += n
+        if t_tot >= seed_budget_s:
+            break
+    return {"value": upd / t_tot if t_tot > 0 else None, "unit": "spin-updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d runs of %d of the stream's requests (in stream order, full N and schedule, fp64), %.1f s"
+                      % (n_runs, n_req, t_tot)}
+
+
 def served(args):
     """Served mixed stream: a capacity pass (all requests at t = 0), then
     Poisson passes at the given fractions of that capacity (default 0.7);
@@ -254,52 +286,42 @@ def served(args):
                    "fraction_of_capacity": head["fraction_of_capacity"], "batching": not args.no_batching,
                    "parallelism": "single GPU, concurrent streams"},
         "latency_ms": {"p50": head["latency_p50_ms"], "p99": head["latency_p99_ms"]},
-        "capacity": cap, "load_sweep": sweep, "roofline": None, "cpu_baseline": None,
+        "capacity": cap, "load_sweep": sweep,
     }
+    # the capacity pass against the roofline of its own work mix: the flops of
+    # every request at the peak of the unit bounding its kernel, over the makespan
+    wr = cap["work_roofline"]
+    total = wr["dense_flop"] + wr["sparse_flop"]
+    line["roofline"] = {"bound": "mfma", "work_weighted": True,
+                        "achieved": round(total / wr["makespan_s"] / 1e12, 3),
+                        "peak": round(total / wr["ideal_s"] / 1e12, 3), "unit": "TFLOP/s",
+                        "frac": round(wr["frac"], 4), "traffic": None,
+                        "mix": {"dense_flop": wr["dense_flop"], "sparse_flop": wr["sparse_flop"],
+                                "dense_peak_tflops": wr["dense_peak_tflops"],
+                                "sparse_peak_tflops": wr["sparse_peak_tflops"]}}
+    line["cpu_baseline"] = None if args.no_cpu_baseline else served_cpu_baseline(base)
+    if line["cpu_baseline"]:
+        log("cpu baseline", line["cpu_baseline"])
     print(json.dumps(line), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sk2000", choices=sorted(DESCRIPTION))
-    ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16", "fp16"],
-                    help="override the workload's arithmetic form")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--rates", default="0.7",
-                    help="served workload: offered loads as fractions of the measured capacity, comma separated")
-    ap.add_argument("--no-batching", action="store_true",
-                    help="served workload: run every request alone on the stream pool")
-    ap.add_argument("--requests", type=int, default=200, help="served workload: number of requests")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 256 MiB device copy (to scale rocprofv3 byte counters)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        return copy_calibration()
-    if args.workload == "served":
-        if args.gpus != 1:
-            print("bench.py measures one GPU.", file=sys.stderr)
-            sys.exit(2)
-        return served(args)
-    if args.gpus != 1:
-        print("bench.py measures one GPU and has no multi-GPU path (runs would shard by index across GPUs, "
-              "with one all-reduce-min of the best energies per instance).  Run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
+SUB_CONFIGS = ["ea2d_L16", "er800", "er20000", "ea3d_L32"]
 
+
+def bench_workload(name, args, *, cpu_budget_s, steps, warmup):
+    """Time every form of one workload (K whole solves on the library's stream,
+    after W untimed ones), its dominant kernel against its roofline, and the
+    CPU oracle on a bounded sample of the same runs.  Returns the fields of a
+    bench line."""
     import numpy as np
     import torch
 
     from paper_1907_05124_amd import inputs as I
     from paper_1907_05124_amd import mars as M
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    w = I.workload(args.workload, seed=args.seed)
+    w = I.workload(name, seed=args.seed)
     N, R = w.instance.N, w.runs
-    log("workload", args.workload, "N=%d R=%d" % (N, R))
+    log("workload", name, "N=%d R=%d" % (N, R))
     inst = M.Instance.from_inputs(w.instance)
     stream = torch.cuda.current_stream()
     dense = isinstance(w.instance, I.DenseInstance)
@@ -322,24 +344,24 @@ def main():
         def solve(sc):
             return inst.solve_ex(R, sc, args.seed, want_best=True, sync=False, stream=stream)
 
-        for i in range(args.warmup):
+        for i in range(warmup):
             solve(sch)
             torch.cuda.synchronize()
-            log(prec, "warmup", i + 1, "done")
+            log(name, prec, "warmup", i + 1, "done")
         # timed region: K whole solves, events on the library's stream
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev[0].record(stream)
-        for k in range(args.steps):
+        for k in range(steps):
             solve(sch)
             ev[k + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+        step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
         ms = float(np.mean(step_ms))
-        log("%s%s: timed %d steps: %.3f ms/step (wall %.3f s)"
-            % (prec, "" if update is None else " " + update, args.steps, ms, wall))
+        log("%s %s%s: timed %d steps: %.3f ms/step (wall %.3f s)"
+            % (name, prec, "" if update is None else " " + update, steps, ms, wall))
         # the same solve once more with host results: update count and summary
         once = inst.solve_ex(R, sch, args.seed, want_best=True, want_spins=True, sync=True, stream=stream)
         res = once["result"]
@@ -374,8 +396,8 @@ def main():
             kname = "k_dense_phase_bf16" if prec == "bf16" else "k_dense_phase_f32"
             out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                                "frac": round(achieved / peak, 4),
-                               "traffic": recorded_traffic(args.workload, prec),
-                               "kernel": kname, "launch_us": round(per_launch_s * 1e6, 3),
+                               "traffic": recorded_traffic(name, prec),
+                               "kernel": kname, "launches": launches, "launch_us": round(per_launch_s * 1e6, 3),
                                "flops_per_launch": flops}
         else:
             # one launch of the LDS-resident solver holds the whole anneal; its
@@ -388,8 +410,8 @@ def main():
             peak = PEAK["fp64_valu"] if prec == "fp64" else PEAK["fp32_valu"]
             out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                                "frac": round(achieved / peak, 4),
-                               "traffic": recorded_traffic(args.workload, prec),
-                               "kernel": "k_lattice_solve" if lat else "k_sparse_solve",
+                               "traffic": recorded_traffic(name, prec),
+                               "kernel": "k_lattice_solve" if lat else "k_sparse_solve", "launches": 1,
                                "launch_us": round(per_launch_s * 1e6, 3), "flops_per_launch": flops}
         return out
 
@@ -402,7 +424,6 @@ def main():
     eligible = [p for p in forms if measured[p]["result"]["best_energy"] <= E_ref + tol]
     head = max(eligible, key=lambda p: measured[p]["value"])
     hm = measured[head]
-    ms, value, res, step_ms, roofline = hm["ms_per_step"], hm["value"], hm["result"], hm["step_ms"], hm["roofline"]
     forms_out = {p: {"value": measured[p]["value"], "ms_per_step": measured[p]["ms_per_step"],
                      "best_energy": measured[p]["result"]["best_energy"],
                      "equal_gap": p in eligible, "tts99_ms": tts99(measured[p], E_ref + tol, R),
@@ -412,7 +433,7 @@ def main():
     # lattice, timed like the forms: a fidelity row, never the headline (its
     # runs fall into the 2-cycles of the synchronous update)
     fidelity = None
-    if args.workload == "ea2d_L16" and not args.precision:
+    if name == "ea2d_L16" and not args.precision:
         jm = measure("fp64", update="jacobi")
         jr = jm["result"]
         fidelity = {"jacobi_fp64": {"value": jm["value"], "ms_per_step": jm["ms_per_step"],
@@ -424,31 +445,82 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline ...")
-        cpu, o_spins, o_energies = cpu_baseline(w, args.seed)
-        log("cpu baseline", cpu)
+        log(name, "cpu baseline ...")
+        cpu, o_spins, o_energies = cpu_baseline(w, args.seed, budget_s=cpu_budget_s)
+        log(name, "cpu baseline", cpu)
         h = getattr(w.instance, "h", None)
         symmetric = h is None or not np.any(h)
         for p in forms:
             forms_out[p]["vs_oracle"] = vs_oracle(measured[p], o_spins, o_energies, symmetric)
-        log("vs oracle", {p: forms_out[p]["vs_oracle"] for p in forms})
+        log(name, "vs oracle", {p: forms_out[p]["vs_oracle"] for p in forms})
+    inst.close()
 
-    dtype = {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "fp16": "f16-store/f32"}[w.schedule.precision]
-    line = {
-        "metric": METRIC, "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
-        "config": {"workload": args.workload, "description": DESCRIPTION[args.workload], "N": N, "runs": R,
+    res = hm["result"]
+    dtype = {"fp32": "f32", "fp64": "f64", "bf16": "bf16", "fp16": "f16-store/f32"}[head]
+    return {
+        "value": hm["value"], "ms_per_step": hm["ms_per_step"], "dtype": dtype,
+        "config": {"workload": name, "description": DESCRIPTION[name], "N": N, "runs": R,
                    "levels": w.schedule.steps, "parallelism": "single GPU, runs batched"},
-        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "latency_ms": {"p50": float(np.percentile(hm["step_ms"], 50)),
+                       "p99": float(np.percentile(hm["step_ms"], 99))},
         "forms": forms_out,
         **({"fidelity": fidelity} if fidelity else {}),
         "result": {"best_energy": res["best_energy"], "best_energy_per_spin": res["best_energy"] / N,
                    "mean_energy_per_spin": res["mean_energy"] / N, "hit_count": res["hit_count"]},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": hm["roofline"], "cpu_baseline": cpu,
+        **({"vs_oracle": forms_out[head]["vs_oracle"]} if cpu else {}),
     }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sk2000", choices=sorted(DESCRIPTION))
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16", "fp16"],
+                    help="override the workload's arithmetic form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="default workload only: leave out the per-configuration records of the other workloads")
+    ap.add_argument("--rates", default="0.7",
+                    help="served workload: offered loads as fractions of the measured capacity, comma separated")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="served workload: run every request alone on the stream pool")
+    ap.add_argument("--requests", type=int, default=200, help="served workload: number of requests")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (to scale rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
+    if args.gpus != 1:
+        print("bench.py measures one GPU and has no multi-GPU path (runs would shard by index across GPUs, "
+              "with one all-reduce-min of the best energies per instance).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "served":
+        return served(args)
+
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    head = bench_workload(args.workload, args, cpu_budget_s=12.0, steps=args.steps, warmup=args.warmup)
+    line = {
+        "metric": METRIC, "value": head["value"], "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": head["dtype"], "data": "synthetic", **{k: v for k, v in head.items()
+                                                                            if k not in ("value", "ms_per_step",
+                                                                                         "dtype")},
+    }
+    if args.workload == "sk2000" and not args.no_configs and not args.precision:
+        # the other configurations of the measurement table, same protocol,
+        # smaller CPU samples (a few seconds each)
+        line["configs"] = {}
+        for name in SUB_CONFIGS:
+            line["configs"][name] = bench_workload(name, args, cpu_budget_s=4.0, steps=args.steps,
+                                                   warmup=args.warmup)
     print(json.dumps(line), flush=True)
-    inst.close()
 
 
 if __name__ == "__main__":

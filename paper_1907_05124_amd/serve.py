@@ -5,9 +5,9 @@ time) are admitted as soon as they have arrived and both an active slot and
 enough HBM are free; each admitted request keeps its couplings and run state
 resident on the GPU while its solve runs on one of a pool of streams, so the
 work of different requests overlaps on the device.  Completed requests free
-their slot and memory; their device buffers are released when the GPU is idle
-or when the memory is needed (releasing device memory synchronises the
-device).
+their slot at once and their memory when the GPU is idle or as soon as an
+arrived request waits for memory (releasing device memory synchronises the
+device, so it is not done while it would only stall running solves).
 
 Dense requests in the BF16 form that are too small to fill the GPU on their
 own (fewer 128 x 128 output tiles per update phase than the chip has compute
@@ -194,7 +194,18 @@ class Scheduler:
         return self.queue[0][0] if self.queue else None
 
     def blocked_on_memory(self, now: float) -> bool:
-        return bool(self.queue) and self.queue[0][0] <= now and self.active < self.max_active
+        """The request at the head of the queue has arrived and has a slot,
+        but its footprint does not fit the memory still held."""
+        if not self.queue or self.queue[0][0] > now or self.active >= self.max_active:
+            return False
+        return self.in_use + footprint_bytes(self.queue[0][2]) > self.budget
+
+    def should_release(self, now: float, running: int) -> bool:
+        """Release the memory of finished requests now: when nothing runs (the
+        synchronising free then stalls nothing) or when an arrived request
+        waits for memory (continuous batching: it is admitted while others
+        still run, instead of after the GPU drains)."""
+        return running == 0 or self.blocked_on_memory(now)
 
 
 # ---------------------------------------------------------------------------
@@ -269,9 +280,10 @@ class MarsServer:
                     else:
                         still.append(job)
                 running = still
-                # release device memory only while nothing runs: a free synchronises
-                # the device, which would stall the running solves
-                if graveyard and not running:
+                # release device memory when nothing runs or a request waits
+                # for memory: a free synchronises the device, which stalls the
+                # running solves, so it is not done while it would only cost
+                if graveyard and sched.should_release(now, len(running)):
                     for inst, fp in graveyard:
                         inst.close()
                         sched.free(fp)

@@ -108,3 +108,58 @@ def test_accept_predicate_keeps_fifo():
     assert [r.rid for r, _ in first] == [0, 1] and sched.active == 2
     rest = sched.admissible(1.0)
     assert [r.rid for r, _ in rest] == [2, 3, 4, 5]
+
+
+def test_memory_of_finished_requests_is_released_while_others_run():
+    """The executor's release rule (Scheduler.should_release): a finished
+    request's memory is held back (a device free synchronises the device)
+    only until an arrived request waits for it.  With a budget for two
+    requests, one long and three short requests arriving at once, the third
+    request must start while the long one still runs, as soon as the first
+    short one has finished."""
+    reqs = _reqs(4, seed=5, rate=0.0)
+    fps = [S.footprint_bytes(r) for r in reqs]
+    budget = fps[0] + max(fps[1:]) + 1
+    assert sum(fps) > budget
+    sched = S.Scheduler(budget, max_active=8)
+    for r in reqs:
+        sched.submit(r)
+    duration = {reqs[0].rid: 10.0, reqs[1].rid: 1.0, reqs[2].rid: 1.0, reqs[3].rid: 1.0}
+    t, running, graveyard, started = 0.0, [], [], {}
+    while sched.queue or running:
+        if graveyard and sched.should_release(t, len(running)):
+            for fp in graveyard:
+                sched.free(fp)
+            graveyard = []
+        for req, fp in sched.admissible(t):
+            running.append((t + duration[req.rid], req, fp))
+            started[req.rid] = t
+        assert sched.in_use <= budget
+        t = min(e for e, _, _ in running)
+        keep = []
+        for e, req, fp in running:
+            if e <= t:
+                sched.finish()
+                graveyard.append(fp)  # memory held until the release rule frees it
+            else:
+                keep.append((e, req, fp))
+        running = keep
+    # requests 0 and 1 start at once; 2 starts when 1 finishes (t = 1), while 0 runs until t = 10
+    assert started[reqs[0].rid] == 0.0 and started[reqs[1].rid] == 0.0
+    assert started[reqs[2].rid] == 1.0 < started[reqs[0].rid] + duration[reqs[0].rid]
+    assert started[reqs[3].rid] == 2.0
+
+
+def test_release_rule_holds_memory_while_nothing_waits():
+    """Without a waiting request the finished memory stays held while solves
+    run (no synchronising free), and is released once nothing runs."""
+    reqs = _reqs(2, seed=6, rate=0.0)
+    sched = S.Scheduler(10 * sum(S.footprint_bytes(r) for r in reqs), max_active=8)
+    for r in reqs:
+        sched.submit(r)
+    admitted = sched.admissible(0.0)
+    assert len(admitted) == 2
+    sched.finish()
+    assert not sched.should_release(0.0, running=1)
+    sched.finish()
+    assert sched.should_release(0.0, running=0)
