@@ -50,12 +50,15 @@ __device__ inline double dense_tanh64(double a)
 // invT64 (or null): the runs' 1/T in fp64 (same layout as invT); with it the
 // update's argument (Phi + h/2) / T and the tanh are evaluated in fp64 and
 // only the new magnetisation is rounded to fp32.
+// One workgroup tile (tile index `tile` of the phase's nrt x nct grid).
+// skip (or null): per 128-run column block, nonzero = leave the tile out (its
+// runs are all frozen and both state buffers already hold their values).
 template <int WM, int WN, int PF, bool RAW>
-__global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
+__device__ __forceinline__ void dense_phase_f32_tile(
     const float *__restrict__ J, int ldj, const float *__restrict__ Mold, float *__restrict__ Mnew, int ldm, int R,
     int p0, int p1, int a0, int nrt, int nct, int kpad, const float *__restrict__ invT,
     const double *__restrict__ invT64, const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax,
-    float *__restrict__ phi)
+    float *__restrict__ phi, int tile, const int32_t *__restrict__ skip)
 {
     constexpr int NT = 64 * WM * WN;
     constexpr int TM = DBM / WM, TN = DBN / WN;  // wave sub-tile
@@ -78,10 +81,12 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
     // run columns: each XCD's L2 then holds its own slice of M plus the
     // phase's J rows, instead of every XCD streaming all of M.
     const int total = nrt * nct;
-    int t = blockIdx.x;
+    int t = tile;
     if ((total & 7) == 0)
         t = (t & 7) * (total >> 3) + (t >> 3);
     const int rt = t % nrt, ct = t / nrt;
+    if (skip && skip[ct])
+        return;
     const int i0 = a0 + rt * DBM;
     const int c0 = ct * DBN;
 
@@ -265,6 +270,62 @@ __global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
                 atomicMax(&dmax[col], __float_as_uint(dl));
         }
     }
+}
+
+// Level state of one run after a sweep (Algorithm 1's repeat ... until, read
+// as d < d_min, with the max_sweeps cap): state[2r] = level index,
+// state[2r+1] = sweeps done at this level, -1 once the run has finished its
+// levels; invT_cur[r] (and invT64_cur[r]) = 1/T of its current level, -1
+// when finished; dmax[r] = bit pattern of the sweep's largest change, read
+// and cleared; runstat[r] = (sweeps, levels, cap hits, -); spl (or null):
+// [R x cap] sweeps run at each visited level.  Returns whether the run still
+// anneals.
+__device__ inline bool dense_advance_one(int r, const float *table, const double *table64, int ldt,
+                                         const int32_t *nlev, int max_sweeps, double d_min, float *invT_cur,
+                                         double *invT64_cur, int32_t *state, int64_t *runstat, uint32_t *dmax,
+                                         int32_t *spl, int cap)
+{
+    int sw = state[2 * r + 1];
+    if (sw < 0)
+        return false;
+    const float d = __uint_as_float(dmax[r]);
+    dmax[r] = 0u;
+    ++sw;
+    runstat[(size_t)r * 4 + 0] += 1;
+    const bool conv = (double)d < d_min;
+    if (conv || sw >= max_sweeps) {
+        if (!conv && max_sweeps > 1)
+            runstat[(size_t)r * 4 + 2] += 1;
+        runstat[(size_t)r * 4 + 1] += 1;
+        if (spl && state[2 * r] < cap)
+            spl[(size_t)r * cap + state[2 * r]] = sw;
+        const int lv = state[2 * r] + 1;
+        state[2 * r] = lv;
+        sw = 0;
+        if (lv >= nlev[r]) {
+            sw = -1;
+            invT_cur[r] = -1.0f;
+            if (table64)
+                invT64_cur[r] = -1.0;
+        } else {
+            invT_cur[r] = table[(size_t)lv * ldt + r];
+            if (table64)
+                invT64_cur[r] = table64[(size_t)lv * ldt + r];
+        }
+    }
+    state[2 * r + 1] = sw;
+    return sw >= 0;
+}
+
+template <int WM, int WN, int PF, bool RAW>
+__global__ __launch_bounds__(64 * WM * WN) void k_dense_phase_f32(
+    const float *__restrict__ J, int ldj, const float *__restrict__ Mold, float *__restrict__ Mnew, int ldm, int R,
+    int p0, int p1, int a0, int nrt, int nct, int kpad, const float *__restrict__ invT,
+    const double *__restrict__ invT64, const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax,
+    float *__restrict__ phi)
+{
+    dense_phase_f32_tile<WM, WN, PF, RAW>(J, ldj, Mold, Mnew, ldm, R, p0, p1, a0, nrt, nct, kpad, invT, invT64, hhalf,
+                                          gamma, dmax, phi, blockIdx.x, nullptr);
 }
 
 }  // namespace mars

@@ -56,12 +56,14 @@ constexpr size_t bf16_phase_lds_bytes()
 
 // One workgroup tile of a phase: tile t (0 <= t < nrt * nct) of the phase's
 // grid; lds: bf16_phase_lds_bytes<BM, BN, BK>() bytes, 16-byte aligned.
+// skip (or null): per BM-run row block, nonzero = leave the tile out (its
+// runs are all frozen and both state buffers already hold their values).
 template <int BM, int BN, int WM, int WN, int PF, int BK, bool BLEND>
 __device__ __forceinline__ void bf16_phase_tile(
     const unsigned short *__restrict__ J, int ldj, const unsigned short *__restrict__ Mold,
     unsigned short *__restrict__ Mnew, int ldk, int R, int p0, int p1, int nrt, int nct, int kpad,
     const float *__restrict__ invT, const float *__restrict__ hhalf, float gamma, uint32_t *__restrict__ dmax,
-    unsigned char *lds, int tile)
+    unsigned char *lds, int tile, const int32_t *__restrict__ skip = nullptr)
 {
     constexpr int NT = 64 * WM * WN;
     constexpr int TM = BM / WM, TN = BN / WN;
@@ -89,6 +91,8 @@ __device__ __forceinline__ void bf16_phase_tile(
     if ((total & 7) == 0)
         t = (t & 7) * (total >> 3) + (t >> 3);
     const int rt = t / nct, ct = t % nct;
+    if (skip && skip[rt])
+        return;
     const int r0 = rt * BM;
     const int i0 = p0 + ct * BN;
 

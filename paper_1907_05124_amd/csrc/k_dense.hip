@@ -227,9 +227,8 @@ void launch_dense_advance_init(int R, const float *table, const double *table64,
                                                           runstat, dmax);
 }
 
-// After a sweep: a level ends when the sweep's largest change d is below
-// d_min or after max_sweeps sweeps; the run then moves to its next level.
-// spl (or null): [R x cap] sweeps run at each visited level of each run.
+// After a sweep: every run's level state (dense_advance_one); active counts
+// the runs still annealing.
 __global__ void k_dense_advance(int R, const float *table, const double *table64, int ldt, const int32_t *nlev,
                                 int max_sweeps, double d_min, float *invT_cur, double *invT64_cur, int32_t *state,
                                 int64_t *runstat, uint32_t *dmax, uint32_t *active, int32_t *spl, int cap)
@@ -237,36 +236,8 @@ __global__ void k_dense_advance(int R, const float *table, const double *table64
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R)
         return;
-    int sw = state[2 * r + 1];
-    if (sw < 0)
-        return;
-    const float d = __uint_as_float(dmax[r]);
-    dmax[r] = 0u;
-    ++sw;
-    runstat[(size_t)r * 4 + 0] += 1;
-    const bool conv = (double)d < d_min;
-    if (conv || sw >= max_sweeps) {
-        if (!conv && max_sweeps > 1)
-            runstat[(size_t)r * 4 + 2] += 1;
-        runstat[(size_t)r * 4 + 1] += 1;
-        if (spl && state[2 * r] < cap)
-            spl[(size_t)r * cap + state[2 * r]] = sw;
-        const int lv = state[2 * r] + 1;
-        state[2 * r] = lv;
-        sw = 0;
-        if (lv >= nlev[r]) {
-            sw = -1;
-            invT_cur[r] = -1.0f;
-            if (table64)
-                invT64_cur[r] = -1.0;
-        } else {
-            invT_cur[r] = table[(size_t)lv * ldt + r];
-            if (table64)
-                invT64_cur[r] = table64[(size_t)lv * ldt + r];
-        }
-    }
-    state[2 * r + 1] = sw;
-    if (sw >= 0)
+    if (dense_advance_one(r, table, table64, ldt, nlev, max_sweeps, d_min, invT_cur, invT64_cur, state, runstat, dmax,
+                          spl, cap))
         atomicAdd(active, 1u);
 }
 

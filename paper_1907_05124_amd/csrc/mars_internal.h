@@ -67,6 +67,7 @@ struct Workspace {
     DevBuf flag;            // small counters
     DevBuf spec;            // Lanczos vectors and coefficients
     DevBuf phi;             // fields of a sequential block
+    DevBuf paper;           // block counters of the one-launch paper schedule
 };
 
 struct Instance {
@@ -198,6 +199,41 @@ void launch_dense_advance(int R, const float *table, const double *table64, int 
                           int64_t *runstat, uint32_t *dmax, uint32_t *active, int32_t *spl, int cap, hipStream_t s);
 // one sweep per level: spl[r * cap + k] = (k < nlev[r])
 void launch_dense_spl_ones(int R, const int32_t *nlev, int32_t *spl, int cap, hipStream_t s);
+
+// The paper's scheduler (several sweeps per level) on dense instances as one
+// cooperative launch (k_dense_paper.hip): phases, the level advance of every
+// run and grid barriers between them, until no run anneals; the final state
+// ends in buffer A (Ma / Ba).  Phase bounds travel in the arguments.
+constexpr int kPaperMaxPhases = 64;
+struct DensePaperArgs {
+    int R, N, Np, B, kmax, ldt, max_sweeps, spl_cap, ntr;  // ntr: 128-run blocks
+    double d_min;
+    float gamma;
+    int pb[kPaperMaxPhases + 1];
+    const float *table;
+    const double *table64;  // fp32 form: fp64 copy of the table (or null)
+    const int32_t *nlev;
+    float *invT_cur;
+    double *invT64_cur;
+    int32_t *state;
+    int64_t *runstat;
+    uint32_t *dmax;
+    int32_t *spl;
+    int32_t *cnt;      // [2 x ntr] active runs per 128-run block, by sweep parity
+    int32_t *frozen;   // [ntr] advances in a row with no active run in the block
+    int32_t *skip;     // [ntr] the block is left out of the products
+    uint32_t *active;  // [2] runs still annealing, by sweep parity
+    const float *hhalf;
+    // fp32 form: state [Np x ldm]
+    const float *J;
+    int ldj, ldm;
+    float *Ma, *Mb;
+    // bf16 form: state [ldr x Np]
+    const unsigned short *Jb;
+    int ldr;
+    unsigned short *Ba, *Bb;
+};
+hipError_t launch_dense_paper(const DensePaperArgs &a, bool bf16, hipStream_t s);
 
 // dense, bf16 form (k_dense_bf16.hip)
 mars_status ensure_bf16_couplings(Instance &I, hipStream_t s);

@@ -98,7 +98,7 @@ static void destroy_instance(Instance *I)
     Workspace &w = I->ws;
     DevBuf *bufs[] = {&w.Ma,      &w.Mb,       &w.invT,   &w.invT64, &w.T0,       &w.nlev, &w.runstat,
                       &w.dmax,    &w.spins,    &w.spad,   &w.energies, &w.partial, &w.result, &w.runstate,
-                      &w.flag,    &w.spec,     &w.phi};
+                      &w.flag,    &w.spec,     &w.phi,      &w.paper};
     for (DevBuf *b : bufs)
         free_buf(*b);
     if (I->own_stream)
@@ -864,24 +864,72 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
         int32_t *state = (int32_t *)(invT_cur + ldr);
         double *invT64_cur = d.table64 ? (double *)(state + 2 * (size_t)ldr) : nullptr;
         uint32_t *dmax = (uint32_t *)w.dmax.p;
-        uint32_t *active = (uint32_t *)w.flag.p;
         launch_dense_advance_init(R, table, d.table64, nlev, invT_cur, invT64_cur, state, runstat, dmax, s);
-        const long long cap = (long long)kmax * sc.max_sweeps + 1;
-        long long done_sweeps = 0;
-        const int chunk = 8;
-        while (done_sweeps < cap) {
-            for (int c = 0; c < chunk; ++c) {
-                sweep(invT_cur, invT64_cur, dmax);
-                launch_fill_u32(active, 0u, 1, s);
-                launch_dense_advance(R, table, d.table64, ldt, nlev, sc.max_sweeps, sc.d_min, invT_cur, invT64_cur,
-                                     state, runstat, dmax, active, spl, spl_cap, s);
-                ++done_sweeps;
+        if (!d.seq && B <= kPaperMaxPhases) {
+            // the whole anneal as one cooperative launch: nothing waits on the host
+            const int ntr = (R + 127) / 128;
+            if ((st = ensure(w.paper, sizeof(int32_t) * 4 * (size_t)ntr + 16)) != MARS_OK)
+                return st;
+            launch_fill_u32((uint32_t *)w.paper.p, 0u, 4 * (size_t)ntr + 4, s);
+            DensePaperArgs a{};
+            a.R = R;
+            a.N = I->N;
+            a.Np = I->Np;
+            a.B = B;
+            a.kmax = kmax;
+            a.ldt = ldt;
+            a.max_sweeps = sc.max_sweeps;
+            a.spl_cap = spl_cap;
+            a.ntr = ntr;
+            a.d_min = sc.d_min;
+            a.gamma = gamma;
+            for (int b = 0; b <= B; ++b)
+                a.pb[b] = pb[b];
+            a.table = table;
+            a.table64 = d.table64;
+            a.nlev = nlev;
+            a.invT_cur = invT_cur;
+            a.invT64_cur = invT64_cur;
+            a.state = state;
+            a.runstat = runstat;
+            a.dmax = dmax;
+            a.spl = spl;
+            int32_t *pw = (int32_t *)w.paper.p;
+            a.cnt = pw;
+            a.frozen = pw + 2 * (size_t)ntr;
+            a.skip = pw + 3 * (size_t)ntr;
+            a.active = (uint32_t *)(pw + 4 * (size_t)ntr);
+            a.hhalf = I->has_h ? I->hhalf : nullptr;
+            a.J = I->J;
+            a.ldj = I->Np;
+            a.ldm = ldm;
+            a.Ma = (float *)d.Ma;
+            a.Mb = (float *)d.Mb;
+            a.Jb = I->Jbf;
+            a.ldr = ldr;
+            a.Ba = (unsigned short *)d.Ma;
+            a.Bb = (unsigned short *)d.Mb;
+            MARS_HIP(launch_dense_paper(a, bf16, s));
+            cur = d.Ma;
+        } else {
+            uint32_t *active = (uint32_t *)w.flag.p;
+            const long long cap = (long long)kmax * sc.max_sweeps + 1;
+            long long done_sweeps = 0;
+            const int chunk = 8;
+            while (done_sweeps < cap) {
+                for (int c = 0; c < chunk; ++c) {
+                    sweep(invT_cur, invT64_cur, dmax);
+                    launch_fill_u32(active, 0u, 1, s);
+                    launch_dense_advance(R, table, d.table64, ldt, nlev, sc.max_sweeps, sc.d_min, invT_cur,
+                                         invT64_cur, state, runstat, dmax, active, spl, spl_cap, s);
+                    ++done_sweeps;
+                }
+                uint32_t h_active = 0;
+                MARS_HIP(hipMemcpyAsync(&h_active, active, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+                MARS_HIP(hipStreamSynchronize(s));
+                if (h_active == 0)
+                    break;
             }
-            uint32_t h_active = 0;
-            MARS_HIP(hipMemcpyAsync(&h_active, active, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-            MARS_HIP(hipStreamSynchronize(s));
-            if (h_active == 0)
-                break;
         }
     }
     return dense_finish(I, d, cur, m_final, spins, E, best_spins, res_dev, best_dev, s);
