@@ -230,14 +230,14 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
             if constexpr (FAST) {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
-                    nw.v[e] = LStore<S>::st(l_tanh_run<sizeof(S) == 4>(phi[e], scale[e]));
+                    nw.v[e] = LStore<S>::st(l_tanh_run<sizeof(S) == 4 ? 2 : 0>(phi[e], scale[e]));
                 lds_put<S, VEC>(reinterpret_cast<S *>(wb + vb), nw);
                 return;
             }
             const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + vb));
 #pragma unroll
             for (int e = 0; e < VEC; ++e) {
-                const C th = l_tanh_run<sizeof(S) == 4>(phi[e], scale[e]);
+                const C th = l_tanh_run<sizeof(S) == 4 ? 2 : 0>(phi[e], scale[e]);
                 const C o = LStore<S>::ld(old.v[e]);
                 C n = DAMP ? ((C)1 - g) * o + g * th : th;
                 n = done[e] ? o : n;  // a finished run keeps its state

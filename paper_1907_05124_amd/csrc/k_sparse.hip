@@ -213,18 +213,18 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                         // convergence tracking: the old value is not needed
 #pragma unroll
                         for (int e = 0; e < VEC; ++e)
-                            nw.v[e] = LStore<S>::st(l_tanh_run<sizeof(S) == 4>(phi[e], scale[e]));
+                            nw.v[e] = lds_keep_sign<S>(l_tanh_run<sizeof(S) == 4 ? 2 : 1>(phi[e], scale[e]));
                         lds_put<S, VEC>(reinterpret_cast<S *>(wb + o_slot), nw);
                         continue;
                     }
                     const Pack<S, VEC> old = lds_get<S, VEC>(reinterpret_cast<const S *>(mb + o_slot));
 #pragma unroll
                     for (int e = 0; e < VEC; ++e) {
-                        const C th = l_tanh_run<sizeof(S) == 4>(phi[e], scale[e]);
+                        const C th = l_tanh_run<sizeof(S) == 4 ? 2 : 1>(phi[e], scale[e]);
                         const C o = LStore<S>::ld(old.v[e]);
                         C n = DAMP ? ((C)1 - g) * o + g * th : th;
                         n = done[e] ? o : n;  // a finished run keeps its state
-                        nw.v[e] = done[e] ? old.v[e] : LStore<S>::st(n);
+                        nw.v[e] = done[e] ? old.v[e] : lds_keep_sign<S>(n);
                         const C dd = n > o ? n - o : o - n;
                         dloc[e] = dd > dloc[e] ? dd : dloc[e];
                     }

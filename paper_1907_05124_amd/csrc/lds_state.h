@@ -226,7 +226,7 @@ static_assert(RUN_AREA_BYTES <= RUN_AREA_MAX, "per-run LDS area exceeds the laun
 // and +1; absolute error ~1e-7 near 0, as for the form on |a|); fp64 divides
 // by T
 //
-// ACCURATE (fp32 storage): the form above has an absolute error of ~1e-7
+// ACC = 2 (fp32 storage): the form above has an absolute error of ~1e-7
 // (the rounding of 2 / (1 + e) near 1), a large relative error where
 // tanh(a) is small: it returns exactly 0 once |a| < ~3e-8, which would pin a
 // magnetisation that decayed at a high temperature at 0 for the rest of the
@@ -237,13 +237,17 @@ static_assert(RUN_AREA_BYTES <= RUN_AREA_MAX, "per-run LDS area exceeds the laun
 // 2.8e-7 for the exp form above 0.625), so the result carries a relative
 // error of a few fp32 units everywhere.  fp16 storage rounds to 2^-11 anyway
 // and keeps the short form.
-template <bool ACCURATE = false>
+//
+// ACC = 1 (fp16 storage of the sparse solver): only tanh(a) = a below
+// |a| = 2^-12 (a^2/3 < 2^-25 relative), so that a decayed value stays
+// nonzero with its sign (see lds_keep_sign) instead of becoming exactly 0.
+template <int ACC = 0>
 __device__ inline float l_tanh_run(float phi, float ts)
 {
     const float x = -phi * ts;
     const float e = __builtin_amdgcn_exp2f(x);
     const float t = __builtin_fmaf(2.0f, __builtin_amdgcn_rcpf(1.0f + e), -1.0f);
-    if constexpr (ACCURATE) {
+    if constexpr (ACC == 2) {
         const float a = x * -0.34657359027997264f;  // x = -2 log2(e) a, so a = -x ln(2) / 2
         const float z = a * a;
         float q = __builtin_fmaf(z, 0.015050967f, -0.051821887f);
@@ -251,14 +255,33 @@ __device__ inline float l_tanh_run(float phi, float ts)
         q = __builtin_fmaf(z, q, -0.33331954f);
         q = __builtin_fmaf(z, q, 0.99999988f);
         return fabsf(a) < 0.625f ? a * q : t;
+    } else if constexpr (ACC == 1) {
+        const float a = x * -0.34657359027997264f;
+        return fabsf(a) < 0x1p-12f ? a : t;
     }
     return t;
+}
+
+// Store of a magnetisation that keeps its sign through fp16 underflow: a
+// nonzero value below half the smallest fp16 subnormal (2^-24) would round to
+// 0, losing the direction a decayed run grows back in once T falls below its
+// instability; it is stored as +-2^-24 instead.  Other storage types store
+// plainly.
+template <typename S>
+__device__ inline S lds_keep_sign(typename LStore<S>::C v)
+{
+    if constexpr (sizeof(S) == 2) {
+        const _Float16 h = (_Float16)v;
+        return (h == (_Float16)0.0f && v != 0.0f) ? (_Float16)copysignf(0x1p-24f, v) : h;
+    } else {
+        return LStore<S>::st(v);
+    }
 }
 // fp64: a = Phi * (1/T) (within an ulp of Phi / T, without a division per
 // update), tanh(a) = expm1(2|a|) / (expm1(2|a|) + 2) with the sign of a
 // (accurate near 0 through expm1; a few ulp), a third of the instructions
 // of the library tanh; |a| > 20 rounds to +-1 in double
-template <bool ACCURATE = false>
+template <int ACC = 0>
 __device__ inline double l_tanh_run(double phi, double invT)
 {
     const double a = phi * invT;
