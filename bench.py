@@ -29,29 +29,44 @@ PEAK = {"fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0, "fp32_valu": 78.
 
 # HBM bytes of one launch of the dominant kernel from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE (KiB per dispatch), scaled by the counters' reading of a plain
-# 256 MiB copy, by (workload, form).  Valid only for the kernel source they
-# were taken on.  The LDS-resident solvers read almost nothing from HBM: what
-# they write is the rounded spins (one byte per spin and run) and run counters.
-TRAFFIC_RECORD = {
-    ("sk2000", "fp32"): {"source": "paper_1907_05124_amd/csrc/dense_phase.h", "sha256_prefix": "4be37f4594fd5dee",
-                         "fetch_kib": 54899.4, "write_kib": 16000.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                         "summary": "profiles/k_dense_phase_f32_sk2000.md"},
-    ("sk2000", "bf16"): {"source": "paper_1907_05124_amd/csrc/dense_phase_bf16.h", "sha256_prefix": "237f59c1c1e9c87f",
-                         "fetch_kib": 26428.9, "write_kib": 8256.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                         "summary": "profiles/k_dense_phase_bf16_sk2000.md"},
-    ("ea3d_L32", "fp16"): {"source": "paper_1907_05124_amd/csrc/k_lattice.hip", "sha256_prefix": "50cee71e34ba1fef",
-                           "fetch_kib": 1023.1, "write_kib": 65600.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                           "summary": "profiles/k_lattice_solve_ea3d_L32.md"},
-    ("ea2d_L16", "fp32"): {"source": "paper_1907_05124_amd/csrc/k_lattice.hip", "sha256_prefix": "50cee71e34ba1fef",
-                           "fetch_kib": 100.6, "write_kib": 288.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                           "summary": "profiles/k_lattice_solve_ea2d_L16.md"},
-    ("er800", "fp32"): {"source": "paper_1907_05124_amd/csrc/k_sparse.hip", "sha256_prefix": "f7d01860c3adc834",
-                        "fetch_kib": 1200.5, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
-                        "summary": "profiles/k_sparse_solve_er800.md"},
-    ("er20000", "fp16"): {"source": "paper_1907_05124_amd/csrc/k_sparse.hip", "sha256_prefix": "f7d01860c3adc834",
-                          "fetch_kib": 3417.6, "write_kib": 165571.5, "fetch_scale": 2.0, "write_scale": 1.0,
-                          "summary": "profiles/k_sparse_solve_er20000.md"},
+# 256 MiB copy, by (workload, form).  Valid only for the kernel sources they
+# were taken on (sha256 over the listed files in order).  The LDS-resident
+# solvers read almost nothing from HBM: what they write is the rounded spins
+# (one byte per spin and run) and run counters.
+_CSRC = "paper_1907_05124_amd/csrc/"
+KERNEL_SOURCES = {
+    "k_dense_phase_f32": [_CSRC + "dense_phase.h", _CSRC + "k_dense.hip", _CSRC + "common_device.h"],
+    "k_dense_phase_bf16": [_CSRC + "dense_phase_bf16.h", _CSRC + "k_dense_bf16.hip", _CSRC + "common_device.h"],
+    "k_lattice_solve": [_CSRC + "k_lattice.hip", _CSRC + "lds_state.h", _CSRC + "common_device.h"],
+    "k_sparse_solve": [_CSRC + "k_sparse.hip", _CSRC + "lds_state.h", _CSRC + "common_device.h"],
 }
+TRAFFIC_RECORD = {
+    ("sk2000", "fp32"): {"kernel": "k_dense_phase_f32", "sha256_prefix": "5e141b5bb4edf753",
+                         "fetch_kib": 60410.0, "write_kib": 27264.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                         "summary": "profiles/k_dense_phase_f32_sk2000.md"},
+    ("sk2000", "bf16"): {"kernel": "k_dense_phase_bf16", "sha256_prefix": "3bf8c2b5c9c21964",
+                         "fetch_kib": 26427.8, "write_kib": 8256.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                         "summary": "profiles/k_dense_phase_bf16_sk2000.md"},
+    ("er800", "fp32"): {"kernel": "k_sparse_solve", "sha256_prefix": "8209892adee16ed2",
+        "fetch_kib": 1203.2, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "summary": "profiles/k_sparse_solve_er800.md"},
+    ("er800", "fp16"): {"kernel": "k_sparse_solve", "sha256_prefix": "8209892adee16ed2",
+        "fetch_kib": 1203.9, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "summary": "profiles/k_sparse_solve_er800.md"},
+    ("er20000", "fp16"): {"kernel": "k_sparse_solve", "sha256_prefix": "8209892adee16ed2",
+        "fetch_kib": 3444.1, "write_kib": 179533.9, "fetch_scale": 2.0, "write_scale": 1.0,
+        "summary": "profiles/k_sparse_solve_er20000.md"},
+    ("ea2d_L16", "fp64"): {"kernel": "k_lattice_solve", "sha256_prefix": "f8f67e4972a37318",
+        "fetch_kib": 111.0, "write_kib": 288.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "summary": "profiles/k_lattice_solve_ea2d_L16.md"},
+    ("ea2d_L16", "fp32"): {"kernel": "k_lattice_solve", "sha256_prefix": "f8f67e4972a37318",
+        "fetch_kib": 111.8, "write_kib": 288.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "summary": "profiles/k_lattice_solve_ea2d_L16.md"},
+    ("ea3d_L32", "fp16"): {"kernel": "k_lattice_solve", "sha256_prefix": "f8f67e4972a37318",
+        "fetch_kib": 1026.8, "write_kib": 65600.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "summary": "profiles/k_lattice_solve_ea3d_L32.md"},
+}
+
 
 DESCRIPTION = {
     "sk2000": "SK N=2000 J~N(0,1/N) (fp32 input), 4096 runs, T0~U[0.25,1.5]*sigma, 300 geometric levels to "
@@ -66,16 +81,22 @@ DESCRIPTION = {
 }
 
 
-def recorded_traffic(workload, precision):
-    """Bytes per launch from the recorded counters, or None if the kernel changed since."""
+def sources_sha(kernel):
+    """sha256 prefix over the sources a kernel is built from."""
     import hashlib
 
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, precision):
+    """Bytes per launch from the recorded counters, or None if the kernel changed since."""
     rec = TRAFFIC_RECORD.get((workload, precision))
-    if rec is None:
+    if rec is None or sources_sha(rec["kernel"]) != rec["sha256_prefix"]:
         return None
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != rec["sha256_prefix"]:
-            return None
     return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
 
 

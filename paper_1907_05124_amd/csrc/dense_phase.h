@@ -35,21 +35,12 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 constexpr int DBM = 128, DBN = 128, DBK = 32;
 
-// tanh in fp64 as expm1(2|a|) / (expm1(2|a|) + 2) with the sign of a
-// (accurate to a few ulp near 0 through expm1; |a| > 20 is +-1 in double)
-__device__ inline double dense_tanh64(double a)
-{
-    const double x = fabs(a);
-    const double e = expm1(2.0 * x);
-    const double t = x > 20.0 ? 1.0 : e / (e + 2.0);
-    return copysign(t, a);
-}
 
 // RAW: instead of the update, write the field Phi = J M + h/2 of the
 // phase's rows to phi (same layout as M) for a sequential pass over them.
 // invT64 (or null): the runs' 1/T in fp64 (same layout as invT); with it the
-// update's argument (Phi + h/2) / T and the tanh are evaluated in fp64 and
-// only the new magnetisation is rounded to fp32.
+// update's argument (Phi + h/2) / T is formed in fp64 from the fp64 field and
+// rounded once before the fp32 tanh.
 // One workgroup tile (tile index `tile` of the phase's nrt x nct grid).
 // skip (or null): per 128-run column block, nonzero = leave the tile out (its
 // runs are all frozen and both state buffers already hold their values).
@@ -251,11 +242,10 @@ __device__ __forceinline__ void dense_phase_f32_tile(
                         const float old = ov[b][a][v];
                         float nw = old;
                         if (it >= 0.0f) {
-                            float th;
-                            if (invT64)
-                                th = (float)dense_tanh64(tot[a][b][v] * itd[b]);
-                            else
-                                th = tanhf((float)tot[a][b][v] * it);
+                            // the argument in fp64 (from the fp64 field and 1/T),
+                            // rounded once; tanh in fp32
+                            const float th = invT64 ? tanhf((float)(tot[a][b][v] * itd[b]))
+                                                    : tanhf((float)tot[a][b][v] * it);
                             nw = damp ? (1.0f - gamma) * old + gamma * th : th;
                         }
                         Mnew[(size_t)row * ldm + col] = nw;
