@@ -38,7 +38,8 @@ KERNEL_SOURCES = {
     "k_dense_phase_f32": [_CSRC + "dense_phase.h", _CSRC + "k_dense.hip", _CSRC + "common_device.h"],
     "k_dense_phase_bf16": [_CSRC + "dense_phase_bf16.h", _CSRC + "k_dense_bf16.hip", _CSRC + "common_device.h"],
     "k_lattice_solve": [_CSRC + "k_lattice.hip", _CSRC + "lds_state.h", _CSRC + "common_device.h"],
-    "k_sparse_solve": [_CSRC + "k_sparse.hip", _CSRC + "lds_state.h", _CSRC + "common_device.h"],
+    "k_sparse_solve": [_CSRC + "sparse_solve.h", _CSRC + "k_sparse.hip", _CSRC + "k_sparse_split.hip",
+                       _CSRC + "lds_state.h", _CSRC + "common_device.h"],
 }
 TRAFFIC_RECORD = {
     ("sk2000", "fp32"): {"kernel": "k_dense_phase_f32", "sha256_prefix": "5e141b5bb4edf753",

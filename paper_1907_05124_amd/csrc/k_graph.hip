@@ -65,6 +65,14 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     int rpw = 1;
     while (rpw < 64 && (size_t)(2 * rpw) * (per_run + RUN_AREA_MAX) + 16 <= lds_cap && 2 * rpw * 256 <= g.R)
         rpw *= 2;
+    // MARS_SPARSE_RPW=<power of two> overrides for sparse instances (tuning),
+    // within the LDS budget
+    if (!lat) {
+        const int want_rpw = env_int("MARS_SPARSE_RPW", 0);
+        if (want_rpw >= 1 && want_rpw <= 64 && (want_rpw & (want_rpw - 1)) == 0 &&
+            (size_t)want_rpw * (per_run + RUN_AREA_MAX) + 16 <= lds_cap)
+            rpw = want_rpw;
+    }
 
     GraphArgs a;
     a.N = N;
@@ -141,8 +149,19 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     if (esz <= 4 && (want == 1 || want == 2 || want == 4) && want <= rpw)
         vec = want;
     const int nq = rpw / vec;
-    // threads per run group: no more than the widest phase has slots (rounded
-    // up to whole waves), at most 1024 per workgroup
+    // lanes per (slot, run group): a long row is split over two lanes (fp32
+    // fields, four runs per group).  On ER N = 800 (48 terms per row, ~40
+    // slots per colour class, 32 runs per workgroup) one lane per slot keeps
+    // about a third of the workgroup's lanes busy in a phase; two lanes per
+    // slot took the solve from 14.1 to 11.7 ms, four (which need two passes
+    // over a 40-slot class at 1024 lanes) to 18.5 ms.  MARS_SPARSE_LPS=1|2|4
+    // overrides (tuning)
+    int lps = (esz <= 4 && vec == 4 && a.long_rows) ? 2 : 1;
+    const int want_lps = env_int("MARS_SPARSE_LPS", 0);
+    if (esz <= 4 && vec == 4 && (want_lps == 1 || want_lps == 2 || want_lps == 4))
+        lps = want_lps;
+    // slots in flight per run group: no more than the widest phase has slots
+    // (rounded up to whole waves), at most 1024 lanes per workgroup
     int widest = 1;
     if (jac) {
         widest = I.nslot;
@@ -150,9 +169,9 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
         for (int c = 0; c < I.ncolours; ++c)
             widest = std::max(widest, I.h_cls[2 * c + 1]);
     }
-    int Tq = std::min(1024 / nq, (widest + 63) / 64 * 64);
-    Tq = std::max(Tq, std::max(1, 64 / nq));
-    e = launch_sparse_solve(a, (int)esz, rpw, Tq, vec, jac, trackd, I.unit, s);
+    int Tq = std::min(1024 / (nq * lps), (widest + 63) / 64 * 64);
+    Tq = std::max(Tq, std::max(1, 64 / (nq * lps)));
+    e = launch_sparse_solve(a, (int)esz, rpw, Tq, vec, lps, jac, trackd, I.unit, s);
     if (e != hipSuccess)
         return hip_error(e, "sparse solve launch");
     return MARS_OK;

@@ -18,6 +18,8 @@ enum Kind { KIND_DENSE = 0, KIND_CSR = 1, KIND_LATTICE = 2 };
 
 constexpr int SELL_H = 8;  // slots per slice of the sparse solver's layout
 constexpr int SELL_W = 4;  // slice widths are padded to a multiple of this
+constexpr int SPARSE_LPS_MAX = 4;  // most lanes the sparse solver splits one slot's row over
+constexpr int SPARSE_READ_AHEAD = 2;  // entry groups of a long row a lane reads ahead
 constexpr size_t RUN_AREA_MAX = 96;  // LDS bytes reserved per run for its level state
 // LDS level table of an LDS-resident solver's block (geometric schedules):
 // 1/T in fp64 for every run and level it visits, then the same in fp32,
@@ -340,7 +342,7 @@ struct GraphArgs {
 };
 
 hipError_t launch_lattice_solve(const GraphArgs &a, int esz, int rpw, bool jac, bool trackd, hipStream_t s);
-hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, bool jac, bool trackd,
-                               bool unit, hipStream_t s);
+hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, int lps, bool jac,
+                               bool trackd, bool unit, hipStream_t s);
 
 }  // namespace mars

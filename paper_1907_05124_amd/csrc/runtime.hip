@@ -503,9 +503,10 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
     bool unit = true;
     for (long long k = 0; k < (long long)rowptr[N]; ++k)
         unit &= (val[k] == 1 || val[k] == -1);
-    // two entry groups of padding after the last slice: the solver reads
-    // that far ahead of the group it sums
-    std::vector<uint32_t> cs(total + (size_t)2 * SELL_W * SELL_H, unit ? (uint32_t)nslot : (uint32_t)nslot | (1u << 24));
+    // entry groups of padding after the last slice: a lane reads up to
+    // SPARSE_READ_AHEAD of its groups past the last one it sums, and a lane's
+    // groups are up to SPARSE_LPS_MAX apart
+    std::vector<uint32_t> cs(total + (size_t)SPARSE_READ_AHEAD * SPARSE_LPS_MAX * SELL_W * SELL_H, unit ? (uint32_t)nslot : (uint32_t)nslot | (1u << 24));
     for (int sl = 0; sl < nslice; ++sl)
         for (int l = 0; l < SELL_H; ++l) {
             const int v = perm[(size_t)sl * SELL_H + l];

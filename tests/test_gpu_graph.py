@@ -118,20 +118,24 @@ RUN_BLOCK_CASES = ["er_pm1", "er_unit", "er_field", "er_dense_isolated", "er_int
 
 
 @pytest.mark.parametrize("case", RUN_BLOCK_CASES)
-@pytest.mark.parametrize("R,vec", [(1031, ""), (2053, "1"), (2053, "2"), (4100, ""), (4100, "2"), (16400, "")])
-def test_one_level_run_blocks(case, R, vec, monkeypatch):
+@pytest.mark.parametrize("R,vec,lps", [(1031, "", ""), (2053, "1", ""), (2053, "2", ""), (4100, "", ""),
+                                       (4100, "2", ""), (16400, "", ""), (1031, "", "4"), (4100, "", "2"),
+                                       (4100, "", "4"), (16400, "", "1")])
+def test_one_level_run_blocks(case, R, vec, lps, monkeypatch):
     """Several runs per workgroup (R >= 1024) and per thread, with a ragged
     last block: one fp32 level within 1e-5 of the oracle.  The sparse path
-    runs four runs per thread by default on blocks of at least four runs;
-    MARS_SPARSE_VEC forces 1 or 2."""
+    runs four runs per lane group by default on blocks of at least four runs;
+    MARS_SPARSE_VEC forces 1 or 2; MARS_SPARSE_LPS forces 1, 2 or 4 lanes per
+    slot (the row split over lanes, with four runs per group)."""
     M = _mars()
-    if vec:
-        monkeypatch.setenv("MARS_SPARSE_VEC", vec)
-    else:
-        monkeypatch.delenv("MARS_SPARSE_VEC", raising=False)
+    for name, val in (("MARS_SPARSE_VEC", vec), ("MARS_SPARSE_LPS", lps)):
+        if val:
+            monkeypatch.setenv(name, val)
+        else:
+            monkeypatch.delenv(name, raising=False)
     inst = CASES[case]()
     sch = _rel_sched(inst, precision="fp32", level_count=1)
-    announce("graph run blocks", case, R, vec)
+    announce("graph run blocks", case, R, vec, lps)
     with M.Instance.from_inputs(inst) as g:
         out = g.solve_ex(R, sch, 29, want_m=True)
     ref = O.solve(inst, R, sch, 29, run_count=R)
@@ -428,3 +432,40 @@ def test_full_size_fp16_storage(name):
     print("[fp16] %s: spin mismatch %.4f, best-energy gap %.2e" % (name, float(np.mean(mism)), gap), flush=True)
     assert np.mean(mism) <= 0.02 and gap <= 5e-3
     assert out["result"]["best_energy"] == E.min()
+
+
+@pytest.mark.parametrize("lps", ["2", "4"])
+@pytest.mark.parametrize("case", ["er_dense_isolated", "er_int8_dense", "er_field"])
+def test_lane_split_variants(case, lps, monkeypatch):
+    """The sparse solver with each slot's row split over 2 or 4 lanes
+    (MARS_SPARSE_LPS), on long rows with isolated vertices, int8 weights and
+    short rows with a field: one damped fp32 level (phased and synchronous)
+    within 1e-5 of the oracle with a ragged run block, the fp16 storage bound
+    of test_one_level_fp16_storage, and the paper's scheduler by replay (runs
+    of one workgroup finishing levels at different sweeps)."""
+    M = _mars()
+    monkeypatch.setenv("MARS_SPARSE_LPS", lps)
+    monkeypatch.delenv("MARS_SPARSE_VEC", raising=False)
+    inst = CASES[case]()
+    R = 1031
+    for update in ("phased", "jacobi"):
+        sch = _rel_sched(inst, precision="fp32", update=update, damping=0.5, level_count=1)
+        announce("graph lane split damped", case, lps, update, R)
+        with M.Instance.from_inputs(inst) as g:
+            out = g.solve_ex(R, sch, 37, want_m=True)
+        ref = O.solve(inst, R, sch, 37, run_count=R)
+        err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
+        assert err <= 1e-5, (update, err)
+    test_one_level_fp16_storage(case, R)
+    s = I.field_scale(inst)
+    R = 2048
+    sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=2.0 * s, c_step=0.2 * s, max_sweeps=1000, d_min=1e-4,
+                     precision="fp32")
+    announce("graph lane split paper schedule", case, lps, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 43, want_m=True, levels_cap=64)
+    spl = out["sweeps_per_level"].cpu().numpy()
+    assert out["result"]["sweeps_executed"] == int(spl.sum())
+    sample = list(range(0, R, R // 32))[:32]
+    check_replay(out["m"].cpu().numpy(), spl, inst, R, sch, 43, "fp32", sample,
+                 label="%s lps=%s" % (case, lps))
