@@ -162,9 +162,14 @@ mars_status mars_describe(const mars_instance *inst, const mars_schedule *sched,
 /* Solve with host outputs (Algorithm 1 over `runs` independent runs, then
  * best-of-runs selection).  best_spins: host int8[N] (may be NULL);
  * energies: host double[runs] (may be NULL); res: host (may be NULL).
- * Blocks until the results are on the host.  Errors: MARS_E_ARG (runs < 1,
- * bad schedule), MARS_E_UNSUPPORTED (precision not available for this
- * instance type, or the state does not fit the chosen kernel),
+ * Blocks until the results are on the host.  Lattice and sparse instances
+ * keep each run's state in LDS when it fits (about 159 KB per run: the
+ * slots times 8, 4 or 2 bytes in fp64, fp32, fp16); a sparse instance
+ * beyond that keeps its state in device memory (a workspace of
+ * (slots + 1) x runs values; about a quarter of the LDS path's throughput
+ * at equal size), a lattice beyond it is refused.  Errors: MARS_E_ARG (runs < 1, bad
+ * schedule), MARS_E_UNSUPPORTED (precision not available for this
+ * instance type, or a lattice whose one-run state does not fit in LDS),
  * MARS_E_OOM, MARS_E_DEVICE. */
 mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
                        int8_t *best_spins, double *energies, mars_result *res);

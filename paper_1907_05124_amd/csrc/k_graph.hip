@@ -40,6 +40,57 @@ static int env_int(const char *name, int dflt)
     return (v && *v) ? std::atoi(v) : dflt;
 }
 
+static size_t graph_esz(int precision)
+{
+    return precision == MARS_FP64 ? 8 : precision == MARS_FP32 ? 4 : precision == MARS_FP16 ? 2 : 0;
+}
+
+static constexpr size_t kLdsCap = 160 * 1024 - 1024;
+
+// sparse instances run with their state in device memory when one run's state
+// does not fit in LDS, or when MARS_GRAPH_GLOBAL=1 (tests of that path at
+// sizes the oracle handles)
+static bool sparse_global(const Instance &I, const mars_schedule &sc)
+{
+    if (I.kind == KIND_LATTICE)
+        return false;
+    const size_t esz = graph_esz(sc.precision);
+    const size_t per_run = ((size_t)I.nslot + 1) * esz * (sc.update == MARS_JACOBI ? 2 : 1);
+    return per_run + 16 + RUN_AREA_MAX > kLdsCap || env_int("MARS_GRAPH_GLOBAL", 0) == 1;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// layout of the device memory of the sparse solver beyond LDS
+struct GlobalLayout {
+    size_t m, m2, rs, tscale, rdone, flag, live, total;
+    int ldr;
+};
+static GlobalLayout global_layout(const Instance &I, const mars_schedule &sc, int R)
+{
+    GlobalLayout L;
+    const size_t esz = graph_esz(sc.precision);
+    const int vec = esz == 8 ? 1 : 4;
+    L.ldr = (R + vec - 1) / vec * vec;
+    const size_t state = align256(((size_t)I.nslot + 1) * L.ldr * esz);
+    L.m = 0;
+    L.m2 = state;
+    L.rs = L.m2 + (sc.update == MARS_JACOBI ? state : 0);
+    L.tscale = L.rs + align256(sizeof(RunState) * L.ldr);
+    L.rdone = L.tscale + align256((esz == 8 ? 8 : 4) * (size_t)L.ldr);
+    L.flag = L.rdone + align256(sizeof(int32_t) * L.ldr);
+    L.live = L.flag + align256(sizeof(uint32_t) * L.ldr);
+    L.total = L.live + 256;
+    return L;
+}
+
+size_t graph_global_bytes(const Instance &I, const mars_schedule &sc, int R)
+{
+    if (graph_esz(sc.precision) == 0 || !sparse_global(I, sc))
+        return 0;
+    return global_layout(I, sc, R).total;
+}
+
 mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s)
 {
     const mars_schedule &sc = *g.sc;
@@ -56,18 +107,22 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     const int N = I.N;
     const size_t rows = lat ? (size_t)N : (size_t)I.nslot + 1;
     const size_t per_run = rows * esz * (jac ? 2 : 1);
-    const size_t lds_cap = 160 * 1024 - 1024;
-    if (per_run + 16 + RUN_AREA_MAX > lds_cap)
-        return set_error(MARS_E_UNSUPPORTED, "the state of one run does not fit in LDS (N too large for this kernel)");
+    const size_t lds_cap = kLdsCap;
+    const bool global = !lat && sparse_global(I, sc);
+    if (!global && per_run + 16 + RUN_AREA_MAX > lds_cap)
+        return set_error(MARS_E_UNSUPPORTED, "the state of one lattice run does not fit in LDS (N too large)");
+    if (global && !g.gscratch)
+        return set_error(MARS_E_ARG, "the sparse solver beyond LDS needs its device memory");
     // runs per workgroup: as many as fit the LDS budget while at least one
     // workgroup per CU (256) remains; more runs per workgroup give each phase
     // more independent (spin, run) items per barrier
     int rpw = 1;
-    while (rpw < 64 && (size_t)(2 * rpw) * (per_run + RUN_AREA_MAX) + 16 <= lds_cap && 2 * rpw * 256 <= g.R)
+    while (!global && rpw < 64 && (size_t)(2 * rpw) * (per_run + RUN_AREA_MAX) + 16 <= lds_cap &&
+           2 * rpw * 256 <= g.R)
         rpw *= 2;
     // MARS_SPARSE_RPW=<power of two> overrides for sparse instances (tuning),
     // within the LDS budget
-    if (!lat) {
+    if (!lat && !global) {
         const int want_rpw = env_int("MARS_SPARSE_RPW", 0);
         if (want_rpw >= 1 && want_rpw <= 64 && (want_rpw & (want_rpw - 1)) == 0 &&
             (size_t)want_rpw * (per_run + RUN_AREA_MAX) + 16 <= lds_cap)
@@ -133,6 +188,40 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
         e = hipGetLastError();
         if (e != hipSuccess)
             return hip_error(e, "graph start-only launch");
+        return MARS_OK;
+    }
+    if (global) {
+        const GlobalLayout L = global_layout(I, sc, g.R);
+        unsigned char *base = static_cast<unsigned char *>(g.gscratch);
+        SparseGlobalArgs ga;
+        ga.a = a;
+        ga.m = base + L.m;
+        ga.m2 = base + L.m2;
+        ga.ldr = L.ldr;
+        {
+            // a chunk's state (every row, its runs) within 64 MB, a quarter of
+            // the MALL; MARS_SPARSE_CHUNK_RUNS overrides (tuning)
+            const int vecg = esz == 8 ? 1 : 4;
+            const size_t row_group = ((size_t)I.nslot + 1) * vecg * esz;
+            size_t ngc = std::max<size_t>(1, ((size_t)64 << 20) / row_group);
+            const int want = env_int("MARS_SPARSE_CHUNK_RUNS", 0);
+            if (want > 0)
+                ngc = std::max<size_t>(1, (size_t)want / vecg);
+            // equal chunks (no nearly empty last chunk)
+            const size_t ngr = (size_t)L.ldr / vecg;
+            const size_t nchunk = (ngr + std::min(ngc, ngr) - 1) / std::min(ngc, ngr);
+            ga.ngc = (int)((ngr + nchunk - 1) / nchunk);
+        }
+        ga.rs = base + L.rs;
+        ga.tscale = base + L.tscale;
+        ga.rdone = reinterpret_cast<int32_t *>(base + L.rdone);
+        ga.flag = reinterpret_cast<uint32_t *>(base + L.flag);
+        ga.live = reinterpret_cast<uint32_t *>(base + L.live);
+        ga.jac = jac ? 1 : 0;
+        ga.unit = I.unit ? 1 : 0;
+        e = launch_sparse_global(ga, (int)esz, s);
+        if (e != hipSuccess)
+            return hip_error(e, "sparse solve launch (state in device memory)");
         return MARS_OK;
     }
     if (lat) {

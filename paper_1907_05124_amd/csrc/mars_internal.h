@@ -70,6 +70,7 @@ struct Workspace {
     DevBuf spec;            // Lanczos vectors and coefficients
     DevBuf phi;             // fields of a sequential block
     DevBuf paper;           // block counters of the one-launch paper schedule
+    DevBuf gstate;          // sparse instances beyond LDS: state and per-run records in device memory
 };
 
 struct Instance {
@@ -298,8 +299,12 @@ struct GraphSolve {
     int64_t *runstat;      // [R x 4]
     int32_t *spl = nullptr;  // [R x spl_cap] sweeps per visited level (zero filled), or null
     int spl_cap = 0;
+    void *gscratch = nullptr;  // graph_global_bytes() of device memory, or null
 };
 mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s);
+// bytes of device memory the solve needs for a sparse instance whose one-run
+// state does not fit in LDS (0: the LDS-resident solver takes it)
+size_t graph_global_bytes(const Instance &I, const mars_schedule &sc, int R);
 
 // kernel arguments of the lattice / sparse solvers
 struct GraphArgs {
@@ -342,6 +347,21 @@ struct GraphArgs {
 };
 
 hipError_t launch_lattice_solve(const GraphArgs &a, int esz, int rpw, bool jac, bool trackd, hipStream_t s);
+
+// the sparse solver with its state in device memory (k_sparse_global.hip)
+struct SparseGlobalArgs {
+    GraphArgs a;
+    void *m, *m2;       // [nslot + 1 rows x ldr] magnetisations (m2: synchronous update only)
+    int ldr;            // row length: runs rounded up to the run group
+    int ngc;            // run groups per chunk of a phase's items
+    void *rs;           // [ldr] per-run level state
+    void *tscale;       // [ldr] per-run factor of the update (run_tscale)
+    int32_t *rdone;     // [ldr] run finished
+    uint32_t *flag;     // [ldr] a change of the sweep reached d_min
+    uint32_t *live;     // [2] alternating words: some run still anneals
+    int jac, unit;
+};
+hipError_t launch_sparse_global(const SparseGlobalArgs &a, int esz, hipStream_t s);
 hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, int lps, bool jac,
                                bool trackd, bool unit, hipStream_t s);
 

@@ -98,7 +98,7 @@ static void destroy_instance(Instance *I)
     Workspace &w = I->ws;
     DevBuf *bufs[] = {&w.Ma,      &w.Mb,       &w.invT,   &w.invT64, &w.T0,       &w.nlev, &w.runstat,
                       &w.dmax,    &w.spins,    &w.spad,   &w.energies, &w.partial, &w.result, &w.runstate,
-                      &w.flag,    &w.spec,     &w.phi,      &w.paper};
+                      &w.flag,    &w.spec,     &w.phi,      &w.paper,  &w.gstate};
     for (DevBuf *b : bufs)
         free_buf(*b);
     if (I->own_stream)
@@ -958,6 +958,12 @@ static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint
     g.runstat = (int64_t *)w.runstat.p;
     g.spl = spl;
     g.spl_cap = spl_cap;
+    const size_t gbytes = graph_global_bytes(*I, sc, R);
+    if (gbytes) {
+        if ((st = ensure(w.gstate, gbytes)) != MARS_OK)
+            return st;
+        g.gscratch = w.gstate.p;
+    }
     if ((st = launch_graph_solve(*I, g, s)) != MARS_OK)
         return st;
     launch_graph_energy(*I, spins, R, E, s);

@@ -1,0 +1,157 @@
+"""Parity of the sparse solver with its state in device memory (instances
+whose one-run state exceeds LDS; forced with MARS_GRAPH_GLOBAL=1 at sizes the
+oracle handles) against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_05124_amd import inputs as I
+from tests.gpu_common import announce, c16_parity, check_replay, require_gpu
+import tests.test_gpu_graph as TG
+from tests.test_gpu_graph import CASES, _decided_spins_agree, _mars, _rel_sched
+
+pytestmark = pytest.mark.gpu
+
+SPARSE = ["er_pm1", "er_unit", "er_field", "er_dense_isolated", "er_int8", "er_int8_dense"]
+
+
+@pytest.fixture
+def forced(monkeypatch):
+    monkeypatch.setenv("MARS_GRAPH_GLOBAL", "1")
+    monkeypatch.delenv("MARS_SPARSE_VEC", raising=False)
+    monkeypatch.delenv("MARS_SPARSE_LPS", raising=False)
+
+
+@pytest.mark.parametrize("case", SPARSE)
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-9)])
+@pytest.mark.parametrize("R", [7, 1031])
+def test_global_one_level(case, precision, tol, R, forced):
+    """One level, phased: every element within the bar (R = 7 and 1031: a
+    ragged last run group)."""
+    M = _mars()
+    inst = CASES[case]()
+    sch = _rel_sched(inst, precision=precision, level_count=1)
+    announce("sparse global one level", case, precision, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 17, want_m=True, want_spins=True)
+    ref = O.solve(inst, R, sch, 17, run_count=R)
+    err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
+    assert err <= tol, err
+    assert out["result"]["sweeps_executed"] == R
+
+
+@pytest.mark.parametrize("case", ["er_pm1", "er_field", "er_dense_isolated"])
+@pytest.mark.parametrize("update", ["phased", "jacobi"])
+def test_global_damped_and_synchronous(case, update, forced):
+    """Damped (g = 0.5) phased and synchronous updates, one fp32 level."""
+    M = _mars()
+    inst = CASES[case]()
+    R = 200
+    sch = _rel_sched(inst, precision="fp32", update=update, damping=0.5, level_count=1)
+    announce("sparse global damped", case, update, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 29, want_m=True)
+    ref = O.solve(inst, R, sch, 29, run_count=R)
+    err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("case", ["er_pm1", "er_field", "er_int8_dense"])
+@pytest.mark.parametrize("precision,levels", [("fp64", 300), ("fp32", 300)])
+def test_global_anneal(case, precision, levels, forced):
+    """Whole geometric anneal: every well-conditioned run (the rule of
+    c16_parity, at most 5 % excluded) within the bar, decided spins equal and
+    energies of equal spin vectors equal."""
+    M = _mars()
+    inst = CASES[case]()
+    sch = _rel_sched(inst, precision=precision, level_count=levels)
+    R = 96
+    announce("sparse global anneal", case, precision, levels, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 23, want_m=True, want_spins=True)
+    ref = O.solve(inst, R, sch, 23, run_count=R)
+    m = out["m"].cpu().numpy()
+    S = out["spins"].cpu().numpy()
+    E = out["energies"].cpu().numpy()
+    c16_parity(m, inst, R, sch, 23, ref, precision, max_excluded=0.05,
+               label="global %s %s level %d" % (case, precision, levels))
+    _decided_spins_agree(S, m, ref, 1e-5 if precision == "fp32" else 1e-9)
+    same = np.all(S == ref["spins"], axis=1)
+    assert np.array_equal(E[same], ref["energy"][same])
+
+
+@pytest.mark.parametrize("case", ["er_field", "er_int8_dense"])
+def test_global_fp16_storage(case, forced):
+    """fp16 storage: the bound of test_one_level_fp16_storage."""
+    TG.test_one_level_fp16_storage(case, 1031)
+
+
+@pytest.mark.parametrize("case", ["er_field", "er_dense_isolated"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_global_paper_schedule_replay(case, precision, forced):
+    """The paper's scheduler (linear decrement, sweeps until d < d_min): the
+    per-run flag of a change reaching d_min decides each level as the largest
+    change would; checked by replay on 32 runs."""
+    M = _mars()
+    inst = CASES[case]()
+    s = I.field_scale(inst)
+    sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=2.0 * s, c_step=0.2 * s, max_sweeps=1000, d_min=1e-4,
+                     precision=precision)
+    R = 1031
+    announce("sparse global paper schedule", case, precision, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 41, want_m=True, levels_cap=64)
+    spl = out["sweeps_per_level"].cpu().numpy()
+    assert out["result"]["sweeps_executed"] == int(spl.sum())
+    sample = list(range(0, R, R // 32))[:32]
+    check_replay(out["m"].cpu().numpy(), spl, inst, R, sch, 41, precision, sample,
+                 label="global %s %s" % (case, precision))
+
+
+def test_global_matches_lds_solver(monkeypatch):
+    """The same fp64 anneal under the paper's scheduler through both solvers:
+    in fp64 with one run per lane group both sum every field in the same
+    entry order and decide each level on the same changes, so the per-level
+    sweep counts and the final magnetisations are identical, bit for bit."""
+    M = _mars()
+    inst = CASES["er_pm1"]()
+    s = I.field_scale(inst)
+    sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=2.0 * s, c_step=0.2 * s, max_sweeps=1000, d_min=1e-4,
+                     precision="fp64")
+    R = 512
+    announce("sparse global vs LDS", R)
+    outs = []
+    for forced_global in ("0", "1"):
+        monkeypatch.setenv("MARS_GRAPH_GLOBAL", forced_global)
+        with M.Instance.from_inputs(inst) as g:
+            outs.append(g.solve_ex(R, sch, 5, want_m=True, levels_cap=64))
+    a, b = outs
+    assert np.array_equal(a["sweeps_per_level"].cpu().numpy(), b["sweeps_per_level"].cpu().numpy())
+    assert np.array_equal(a["m"].cpu().numpy(), b["m"].cpu().numpy())
+
+
+def test_beyond_lds_sampled(monkeypatch):
+    """An instance whose one-run fp32 state exceeds LDS (ER N = 48000,
+    average degree 4, 192 KB per run), so the solver takes the device-memory
+    path without being forced: 16 sampled runs of a 256-run anneal within
+    1e-5 of the oracle on every well-conditioned run (at most 10 %
+    excluded), decided spins equal."""
+    monkeypatch.delenv("MARS_GRAPH_GLOBAL", raising=False)
+    M = _mars()
+    require_gpu()
+    inst = I.er_instance(48000, 3, p=4.0 / 47999, weights="pm1")
+    sch = _rel_sched(inst, precision="fp32", steps=100)
+    R = 256
+    announce("sparse beyond LDS", inst.N, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 7, want_m=True, want_spins=True)
+    m = out["m"].cpu().numpy()
+    S = out["spins"].cpu().numpy()
+    excl = 0.0
+    for r0 in (0, 131, 248):
+        ref = O.solve(inst, R, sch, 7, run_begin=r0, run_count=8 if r0 != 131 else 1)
+        n = ref["m"].shape[1]
+        excl += n * c16_parity(m[:, r0:r0 + n], inst, R, sch, 7, ref, "fp32", run_begin=r0, max_excluded=1.0,
+                               label="ER N=48000 runs %d..%d" % (r0, r0 + n - 1))
+        _decided_spins_agree(S[r0:r0 + n], m[:, r0:r0 + n], ref, 1e-5)
+    assert excl / 17 <= 0.1
