@@ -262,7 +262,7 @@ def served(args):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    server = S.MarsServer(max_active=8, n_streams=4, batching=not args.no_batching)
+    server = S.MarsServer(max_active=8, n_streams=4, batching=not args.no_batching, grouping=not args.no_batching)
     fracs = [float(x) for x in args.rates.split(",")]
 
     base = S.mixed_stream(args.requests, 1e9, seed=args.seed)
@@ -509,7 +509,7 @@ def main():
     ap.add_argument("--rates", default="0.7",
                     help="served workload: offered loads as fractions of the measured capacity, comma separated")
     ap.add_argument("--no-batching", action="store_true",
-                    help="served workload: run every request alone on the stream pool")
+                    help="served workload: run every request alone on the stream pool (no dense batch, no sparse groups)")
     ap.add_argument("--requests", type=int, default=200, help="served workload: number of requests")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (to scale rocprofv3 byte counters)")

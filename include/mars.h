@@ -215,6 +215,31 @@ mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_sched
                              const void *m0, const double *T0, void *m_final, int8_t *spins, double *energies,
                              int8_t *best_spins, mars_result *res_pinned, void *stream);
 
+/* Several lattice or sparse solves enqueued together on one stream, for a
+ * server that admits many small requests at once (one launch per request
+ * leaves the GPU mostly idle when each has few runs).  Member i is the solve
+ * of mars_solve_async(insts[i], runs[i], &scheds[i], seeds[i], NULL, NULL,
+ * NULL, NULL, energies[i], best_spins[i], &res_pinned[i], stream), with the
+ * same outputs bit for bit; sparse members whose anneal runs on the same
+ * instantiation of the LDS-resident solver (storage precision, runs per lane
+ * group, lanes per slot, update, field, weights, damping, stopping rule)
+ * share one launch of it, each on its own workgroups.  Lattice members and
+ * sparse members beyond LDS are enqueued as they would be alone.  Runs may
+ * differ between members; each run's trajectory is independent of the
+ * others (Algorithm 1 per run).
+ *   count: 1 to 64; the instances are distinct, on one device, not dense.
+ *   best_spins, energies: arrays of count DEVICE pointers (int8 [N_i],
+ *            double [runs_i]); the arrays or any entry may be NULL.
+ *   res_pinned: HOST pinned mars_result [count], or NULL.
+ * Returns after enqueueing; outputs are valid once the stream has passed the
+ * enqueued work.  Errors: MARS_E_ARG (count, NULL arrays, an instance twice
+ * or on another device, runs, schedules), MARS_E_UNSUPPORTED (a dense
+ * instance, or as mars_solve), MARS_E_OOM, MARS_E_DEVICE; validation
+ * precedes any enqueued work. */
+mars_status mars_solve_group_async(int32_t count, mars_instance *const *insts, const int32_t *runs,
+                                   const mars_schedule *scheds, const uint64_t *seeds, int8_t *const *best_spins,
+                                   double *const *energies, mars_result *res_pinned, void *stream);
+
 /* Exact energies (eq. (2)) of R spin vectors.  spins: DEVICE int8 [R x N]
  * (values +-1); energies: DEVICE double [R].  stream as in mars_solve_ex;
  * the call returns after enqueueing.  Errors: MARS_E_ARG, MARS_E_DEVICE. */

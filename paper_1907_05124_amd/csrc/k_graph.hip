@@ -91,7 +91,10 @@ size_t graph_global_bytes(const Instance &I, const mars_schedule &sc, int R)
     return global_layout(I, sc, R).total;
 }
 
-mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s)
+// Enqueues the solve's anneal, or, for a sparse solve on the LDS-resident
+// solver when `plan` is given, fills *plan for a shared launch and enqueues
+// nothing (plan->fn stays null when the solve was enqueued).
+static mars_status graph_solve_or_plan(const Instance &I, const GraphSolve &g, hipStream_t s, SparsePlan *plan)
 {
     const mars_schedule &sc = *g.sc;
     const bool jac = sc.update == MARS_JACOBI;
@@ -260,10 +263,27 @@ mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream
     }
     int Tq = std::min(1024 / (nq * lps), (widest + 63) / 64 * 64);
     Tq = std::max(Tq, std::max(1, 64 / (nq * lps)));
+    if (plan) {
+        e = plan_sparse_solve(a, (int)esz, rpw, Tq, vec, lps, jac, trackd, I.unit, plan);
+        if (e != hipSuccess)
+            return hip_error(e, "sparse solve plan");
+        return MARS_OK;
+    }
     e = launch_sparse_solve(a, (int)esz, rpw, Tq, vec, lps, jac, trackd, I.unit, s);
     if (e != hipSuccess)
         return hip_error(e, "sparse solve launch");
     return MARS_OK;
+}
+
+mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s)
+{
+    return graph_solve_or_plan(I, g, s, nullptr);
+}
+
+mars_status plan_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s, SparsePlan *plan)
+{
+    plan->fn = nullptr;
+    return graph_solve_or_plan(I, g, s, plan);
 }
 
 }  // namespace mars

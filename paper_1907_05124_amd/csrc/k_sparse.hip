@@ -13,8 +13,8 @@ namespace mars {
 // Tq: slots in flight per run group; vec: runs per lane group (1, 2 or 4,
 // dividing rpw); lps: lanes per (slot, run group) (1, or 2 or 4 dividing vec
 // with fp32 fields)
-hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, int lps, bool jac,
-                               bool trackd, bool unit, hipStream_t s)
+hipError_t plan_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, int lps, bool jac, bool trackd,
+                             bool unit, SparsePlan *plan)
 {
     int lg = 0;
     while ((1 << lg) < rpw)
@@ -42,18 +42,68 @@ hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int
     const int threads = Tq * nq * lps;
     if (threads > 1024 || Tq < 1 || threads % 64 != 0)
         return hipErrorInvalidConfiguration;
-    GraphArgs b = a;
-    b.ttab = level_table_fit(a.ttab, rpw, base_lds, threads, (a.R + rpw - 1) / rpw);
-    const size_t lds = base_lds + level_table_bytes(rpw, b.ttab);
+    plan->fn = reinterpret_cast<const void *>(fn);
+    plan->args = a;
+    plan->args.ttab = level_table_fit(a.ttab, rpw, base_lds, threads, (a.R + rpw - 1) / rpw);
+    plan->lg = lg;
+    plan->blocks = (a.R + rpw - 1) / rpw;
+    plan->threads = threads;
+    plan->lds = base_lds + level_table_bytes(rpw, plan->args.ttab);
+    return hipSuccess;
+}
+
+// Launches solves with one kernel: one plan alone (no descriptor), or several
+// of the same kernel through the group descriptor (host_desc is filled and
+// copied to dev_desc on the stream; both stay untouched until the launch has
+// run).
+hipError_t launch_sparse_plans(const SparsePlan *plans, int n, GraphGroup *host_desc, GraphGroup *dev_desc,
+                               hipStream_t s)
+{
+    if (n < 1 || n > GRAPH_GROUP_MAX)
+        return hipErrorInvalidValue;
+    int blocks = 0, threads = 0;
+    size_t lds = 0;
+    for (int k = 0; k < n; ++k) {
+        if (plans[k].fn != plans[0].fn)
+            return hipErrorInvalidValue;
+        blocks += plans[k].blocks;
+        threads = std::max(threads, plans[k].threads);
+        lds = std::max(lds, plans[k].lds);
+    }
+    SparseFn fn = reinterpret_cast<SparseFn>(const_cast<void *>(plans[0].fn));
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(plans[0].fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
     }
-    dim3 grid((a.R + rpw - 1) / rpw), block(threads);
-    hipLaunchKernelGGL(fn, grid, block, lds, s, b, lg);
+    const GraphGroup *grp = nullptr;
+    if (n > 1) {
+        if (!host_desc || !dev_desc)
+            return hipErrorInvalidValue;
+        host_desc->count = n;
+        host_desc->first[0] = 0;
+        for (int k = 0; k < n; ++k) {
+            host_desc->first[k + 1] = host_desc->first[k] + plans[k].blocks;
+            host_desc->lg[k] = plans[k].lg;
+            host_desc->args[k] = plans[k].args;
+        }
+        hipError_t e = hipMemcpyAsync(dev_desc, host_desc, sizeof(GraphGroup), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return e;
+        grp = dev_desc;
+    }
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(threads), lds, s, plans[0].args, plans[0].lg, grp);
     return hipGetLastError();
+}
+
+hipError_t launch_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, int lps, bool jac,
+                               bool trackd, bool unit, hipStream_t s)
+{
+    SparsePlan p;
+    hipError_t e = plan_sparse_solve(a, esz, rpw, Tq, vec, lps, jac, trackd, unit, &p);
+    if (e != hipSuccess)
+        return e;
+    return launch_sparse_plans(&p, 1, nullptr, nullptr, s);
 }
 
 }  // namespace mars

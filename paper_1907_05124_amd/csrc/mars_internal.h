@@ -71,6 +71,7 @@ struct Workspace {
     DevBuf phi;             // fields of a sequential block
     DevBuf paper;           // block counters of the one-launch paper schedule
     DevBuf gstate;          // sparse instances beyond LDS: state and per-run records in device memory
+    DevBuf grp;             // descriptor of a shared sparse launch (GraphGroup)
 };
 
 struct Instance {
@@ -109,8 +110,8 @@ struct Instance {
     // the SELL_H slots of a slice read 128 contiguous bytes per group), each
     // (neighbour slot) | (uint8(weight) << 24), or, when every weight is
     // +-1 (unit), (neighbour slot) | (weight < 0) << 31; a missing entry
-    // names the all-zero row nslot with weight +1; two groups of such
-    // entries (2 x SELL_W x SELL_H) follow the last slice
+    // names the all-zero row nslot with weight +1; SPARSE_READ_AHEAD x
+    // SPARSE_LPS_MAX groups of such entries follow the last slice
     int nslot = 0;
     bool unit = false;            // every |weight| == 1
     int32_t *perm = nullptr;      // [nslot] slot -> vertex, -1 for padding
@@ -135,6 +136,11 @@ struct Instance {
     bool done_recorded = false;
     bool in_batch = false;  // owned by a batch until its member finishes
     double tick_s = 0.0;    // seconds per tick of the device's constant-rate clock
+    // descriptor of a shared sparse launch this instance led: host copy (kept
+    // until its copy to the device has run, grp_event) and device copy
+    std::vector<unsigned char> grp_host;
+    hipEvent_t grp_event = nullptr;
+    bool grp_pending = false;
     Workspace ws;
     std::mutex mu;
 };
@@ -302,6 +308,11 @@ struct GraphSolve {
     void *gscratch = nullptr;  // graph_global_bytes() of device memory, or null
 };
 mars_status launch_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s);
+struct SparsePlan;
+// as launch_graph_solve, but a sparse solve on the LDS-resident solver is
+// planned (*plan, plan->fn set) instead of enqueued, for a shared launch;
+// other solves are enqueued (plan->fn null)
+mars_status plan_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s, SparsePlan *plan);
 // bytes of device memory the solve needs for a sparse instance whose one-run
 // state does not fit in LDS (0: the LDS-resident solver takes it)
 size_t graph_global_bytes(const Instance &I, const mars_schedule &sc, int R);
@@ -347,6 +358,31 @@ struct GraphArgs {
 };
 
 hipError_t launch_lattice_solve(const GraphArgs &a, int esz, int rpw, bool jac, bool trackd, hipStream_t s);
+
+// Several sparse solves in one launch of the LDS-resident solver: instance k
+// owns blocks first[k] .. first[k + 1] - 1 (block index within it = block -
+// first[k]) with its own arguments and runs per workgroup (2^lg[k]).
+constexpr int GRAPH_GROUP_MAX = 64;
+struct GraphGroup {
+    int count;
+    int first[GRAPH_GROUP_MAX + 1];
+    int lg[GRAPH_GROUP_MAX];
+    GraphArgs args[GRAPH_GROUP_MAX];
+};
+// How one sparse solve launches the LDS-resident solver: the kernel
+// (instantiation), its arguments, and the launch shape.  Solves whose kernels
+// agree can share one launch (the block shape is the largest of theirs: the
+// kernel derives its slots in flight from it; the LDS size the largest).
+struct SparsePlan {
+    const void *fn = nullptr;
+    GraphArgs args;
+    int lg = 0, blocks = 0, threads = 0;
+    size_t lds = 0;
+};
+hipError_t plan_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int vec, int lps, bool jac, bool trackd,
+                             bool unit, SparsePlan *plan);
+hipError_t launch_sparse_plans(const SparsePlan *plans, int n, GraphGroup *host_desc, GraphGroup *dev_desc,
+                               hipStream_t s);
 
 // the sparse solver with its state in device memory (k_sparse_global.hip)
 struct SparseGlobalArgs {

@@ -85,6 +85,10 @@ static void destroy_instance(Instance *I)
     (void)hipSetDevice(I->device);
     if (I->own_stream)
         (void)hipStreamSynchronize(I->own_stream);
+    if (I->grp_event) {
+        (void)hipEventSynchronize(I->grp_event);
+        (void)hipEventDestroy(I->grp_event);
+    }
     if (I->done_event) {
         (void)hipEventSynchronize(I->done_event);
         (void)hipEventDestroy(I->done_event);
@@ -98,7 +102,7 @@ static void destroy_instance(Instance *I)
     Workspace &w = I->ws;
     DevBuf *bufs[] = {&w.Ma,      &w.Mb,       &w.invT,   &w.invT64, &w.T0,       &w.nlev, &w.runstat,
                       &w.dmax,    &w.spins,    &w.spad,   &w.energies, &w.partial, &w.result, &w.runstate,
-                      &w.flag,    &w.spec,     &w.phi,      &w.paper,  &w.gstate};
+                      &w.flag,    &w.spec,     &w.phi,      &w.paper,  &w.gstate, &w.grp};
     for (DevBuf *b : bufs)
         free_buf(*b);
     if (I->own_stream)
@@ -936,9 +940,13 @@ static mars_status solve_dense(Instance *I, int R, const mars_schedule &sc, uint
     return dense_finish(I, d, cur, m_final, spins, E, best_spins, res_dev, best_dev, s);
 }
 
-static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const void *m0,
-                               const double *T0in, void *m_final, int8_t *spins, double *E, int8_t *best_spins,
-                               int32_t *spl, int spl_cap, mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+// A lattice/sparse solve in three parts, so that several solves can share
+// the anneal's launch: the starting temperatures and the solve description
+// (graph_pre), the anneal (launch_graph_solve, or a shared launch), then
+// exact energies, best run and best spins (graph_post).
+static mars_status graph_pre(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const void *m0,
+                             const double *T0in, void *m_final, int8_t *spins, double *E, int32_t *spl, int spl_cap,
+                             GraphSolve *g, hipStream_t s)
 {
     Workspace &w = I->ws;
     mars_status st;
@@ -946,32 +954,48 @@ static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint
         return st;
     double *T0 = (double *)w.T0.p;
     launch_init_T0(seed, R, sc.T_lo, sc.T_hi, T0in, T0, s);
-    GraphSolve g;
-    g.sc = &sc;
-    g.seed = seed;
-    g.R = R;
-    g.m0 = m0;
-    g.T0 = T0;
-    g.m_final = m_final;
-    g.spins = spins;
-    g.energies = E;
-    g.runstat = (int64_t *)w.runstat.p;
-    g.spl = spl;
-    g.spl_cap = spl_cap;
+    g->sc = &sc;
+    g->seed = seed;
+    g->R = R;
+    g->m0 = m0;
+    g->T0 = T0;
+    g->m_final = m_final;
+    g->spins = spins;
+    g->energies = E;
+    g->runstat = (int64_t *)w.runstat.p;
+    g->spl = spl;
+    g->spl_cap = spl_cap;
     const size_t gbytes = graph_global_bytes(*I, sc, R);
     if (gbytes) {
         if ((st = ensure(w.gstate, gbytes)) != MARS_OK)
             return st;
-        g.gscratch = w.gstate.p;
+        g->gscratch = w.gstate.p;
     }
-    if ((st = launch_graph_solve(*I, g, s)) != MARS_OK)
-        return st;
-    launch_graph_energy(*I, spins, R, E, s);
-    launch_argmin(E, T0, g.runstat, R, I->N, I->wsum, res_dev, best_dev, I->tick_s, s);
+    return MARS_OK;
+}
+
+static mars_status graph_post(Instance *I, const GraphSolve &g, int8_t *best_spins, mars_result *res_dev,
+                              int32_t *best_dev, hipStream_t s)
+{
+    launch_graph_energy(*I, g.spins, g.R, g.energies, s);
+    launch_argmin(g.energies, g.T0, g.runstat, g.R, I->N, I->wsum, res_dev, best_dev, I->tick_s, s);
     if (best_spins)
-        launch_gather_best(spins, I->N, best_dev, I->N, best_spins, s);
+        launch_gather_best(g.spins, I->N, best_dev, I->N, best_spins, s);
     MARS_HIP(hipGetLastError());
     return MARS_OK;
+}
+
+static mars_status solve_graph(Instance *I, int R, const mars_schedule &sc, uint64_t seed, const void *m0,
+                               const double *T0in, void *m_final, int8_t *spins, double *E, int8_t *best_spins,
+                               int32_t *spl, int spl_cap, mars_result *res_dev, int32_t *best_dev, hipStream_t s)
+{
+    GraphSolve g;
+    mars_status st = graph_pre(I, R, sc, seed, m0, T0in, m_final, spins, E, spl, spl_cap, &g, s);
+    if (st != MARS_OK)
+        return st;
+    if ((st = launch_graph_solve(*I, g, s)) != MARS_OK)
+        return st;
+    return graph_post(I, g, best_spins, res_dev, best_dev, s);
 }
 
 // Stream ordering of the shared workspace: wait for the instance's previous
@@ -1412,6 +1436,121 @@ mars_status mars_solve_async(mars_instance *inst, int32_t runs, const mars_sched
         return st;
     MARS_HIP(hipMemcpyAsync(res_pinned, I->ws.result.p, sizeof(mars_result), hipMemcpyDeviceToHost, s));
     return order_end(I, s);
+}
+
+mars_status mars_solve_group_async(int32_t count, mars_instance *const *insts, const int32_t *runs,
+                                   const mars_schedule *scheds, const uint64_t *seeds, int8_t *const *best_spins,
+                                   double *const *energies, mars_result *res_pinned, void *stream)
+{
+    if (count < 1 || count > GRAPH_GROUP_MAX)
+        return set_error(MARS_E_ARG, "a group holds 1 to 64 solves");
+    if (!insts || !runs || !scheds || !seeds)
+        return set_error(MARS_E_ARG, "instances, runs, schedules and seeds must be given");
+    std::vector<Instance *> L(count);
+    for (int i = 0; i < count; ++i) {
+        L[i] = reinterpret_cast<Instance *>(insts[i]);
+        if (!L[i])
+            return set_error(MARS_E_ARG, "instance is NULL");
+        for (int j = 0; j < i; ++j)
+            if (L[j] == L[i])
+                return set_error(MARS_E_ARG, "an instance appears twice in a group (solves share its workspace)");
+    }
+    // lock every member (in address order, so that concurrent groups cannot
+    // deadlock)
+    std::vector<Instance *> order(L);
+    std::sort(order.begin(), order.end());
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (Instance *I : order)
+        locks.emplace_back(I->mu);
+    for (int i = 0; i < count; ++i) {
+        Instance *I = L[i];
+        if (I->in_batch)
+            return set_error(MARS_E_ARG, "the instance belongs to a batch until its solve finishes");
+        if (I->kind == KIND_DENSE)
+            return set_error(MARS_E_UNSUPPORTED, "groups hold lattice and sparse instances");
+        if (I->device != L[0]->device)
+            return set_error(MARS_E_ARG, "the instances of a group are on one device");
+        if (runs[i] < 1 || runs[i] >= (1 << 30))
+            return set_error(MARS_E_ARG, "runs must be >= 1 and < 2^30");
+        mars_status st = check_schedule(&scheds[i], I->kind);
+        if (st != MARS_OK)
+            return st;
+    }
+    MARS_HIP(hipSetDevice(L[0]->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::vector<GraphSolve> G(count);
+    std::vector<SparsePlan> P(count);
+    mars_status st;
+    for (int i = 0; i < count; ++i) {
+        Instance *I = L[i];
+        Workspace &w = I->ws;
+        const int R = runs[i];
+        if ((st = order_begin(I, s)) != MARS_OK)
+            return st;
+        if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK ||
+            (st = ensure(w.spins, (size_t)R * I->N)) != MARS_OK)
+            return st;
+        double *E = energies ? energies[i] : nullptr;
+        if (!E) {
+            if ((st = ensure(w.energies, sizeof(double) * R)) != MARS_OK)
+                return st;
+            E = (double *)w.energies.p;
+        }
+        launch_stamp(result_stamp((mars_result *)w.result.p), s);
+        if ((st = graph_pre(I, R, scheds[i], seeds[i], nullptr, nullptr, nullptr, (int8_t *)w.spins.p, E, nullptr,
+                            0, &G[i], s)) != MARS_OK)
+            return st;
+        // a sparse solve on the LDS-resident solver is planned; any other is
+        // enqueued here
+        if ((st = plan_graph_solve(*I, G[i], s, &P[i])) != MARS_OK)
+            return st;
+    }
+    // one launch per kernel among the planned solves
+    std::vector<bool> launched(count, false);
+    for (int i = 0; i < count; ++i) {
+        if (!P[i].fn || launched[i])
+            continue;
+        std::vector<SparsePlan> same;
+        for (int j = i; j < count; ++j)
+            if (!launched[j] && P[j].fn == P[i].fn) {
+                same.push_back(P[j]);
+                launched[j] = true;
+            }
+        GraphGroup *hd = nullptr, *dd = nullptr;
+        Instance *lead = L[i];
+        if (same.size() > 1) {
+            // the leader's descriptor: its previous copy must have run before
+            // the host copy is rewritten
+            if (lead->grp_pending)
+                MARS_HIP(hipEventSynchronize(lead->grp_event));
+            if (!lead->grp_event)
+                MARS_HIP(hipEventCreateWithFlags(&lead->grp_event, hipEventDisableTiming));
+            lead->grp_host.resize(sizeof(GraphGroup));
+            if ((st = ensure(lead->ws.grp, sizeof(GraphGroup))) != MARS_OK)
+                return st;
+            hd = reinterpret_cast<GraphGroup *>(lead->grp_host.data());
+            dd = reinterpret_cast<GraphGroup *>(lead->ws.grp.p);
+        }
+        hipError_t e = launch_sparse_plans(same.data(), (int)same.size(), hd, dd, s);
+        if (e != hipSuccess)
+            return hip_error(e, "shared sparse solve launch");
+        if (hd) {
+            MARS_HIP(hipEventRecord(lead->grp_event, s));
+            lead->grp_pending = true;
+        }
+    }
+    for (int i = 0; i < count; ++i) {
+        Instance *I = L[i];
+        mars_result *res_dev = (mars_result *)I->ws.result.p;
+        if ((st = graph_post(I, G[i], best_spins ? best_spins[i] : nullptr, res_dev, result_best(res_dev), s)) !=
+            MARS_OK)
+            return st;
+        if (res_pinned)
+            MARS_HIP(hipMemcpyAsync(&res_pinned[i], res_dev, sizeof(mars_result), hipMemcpyDeviceToHost, s));
+        if ((st = order_end(I, s)) != MARS_OK)
+            return st;
+    }
+    return MARS_OK;
 }
 
 mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,

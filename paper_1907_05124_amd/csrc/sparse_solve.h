@@ -91,9 +91,22 @@ __device__ __forceinline__ void split_reduce(const float (&phi)[VEC], float (&ow
 }
 
 template <typename S, int VEC, int LPS, bool JAC, bool TRACKD, bool HAS_H, bool UNIT, bool DAMP>
-__global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
+__global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a_one, int lg_one, const GraphGroup *grp)
 {
     typedef typename LStore<S>::C C;
+    // one instance (grp null), or the instances of a group, each with its own
+    // consecutive blocks: the block finds its instance and its index there
+    int bid = blockIdx.x;
+    int lg_rpw = lg_one;
+    GraphArgs a = a_one;
+    if (grp) {
+        int k = 0;
+        while (k + 1 < grp->count && bid >= grp->first[k + 1])
+            ++k;
+        bid -= grp->first[k];
+        lg_rpw = grp->lg[k];
+        a = grp->args[k];
+    }
     static_assert(LPS == 1 || (sizeof(C) == 4 && VEC % LPS == 0), "lane split needs fp32 fields and LPS | VEC");
     constexpr int OWN = VEC / LPS;  // runs each lane updates
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -112,7 +125,7 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
     const int q0_io = (threadIdx.x % nq) * VEC;
     const int tq_io = threadIdx.x / nq;
     const int Tq_io = blockDim.x / nq;
-    const int run0_io = blockIdx.x * rpw + q0_io;
+    const int run0_io = bid * rpw + q0_io;
     // sweeps: LPS adjacent lanes per (slot, run group)
     const int part = LPS > 1 ? (int)(threadIdx.x % LPS) : 0;
     const int q0 = ((threadIdx.x / LPS) % nq) * VEC;
@@ -137,7 +150,7 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
             lds_put<S, VEC>(&m2[((size_t)i << lg_rpw) + q0_io], p);
     }
     for (int q = threadIdx.x; q < rpw; q += blockDim.x) {
-        const int r = blockIdx.x * rpw + q;
+        const int r = bid * rpw + q;
         rsl[q].start(a.rs, r < a.R ? a.T0[r] : 1.0, r < a.R);
         dq[q] = 0;
     }
@@ -364,7 +377,7 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
         for (int q = threadIdx.x; q < rpw; q += blockDim.x) {
             rsl[q].end_sweep(a.rs, __uint_as_float(dq[q]), TRACKD, a.max_sweeps, a.d_min,
                              ttab ? tT + (size_t)q * ttab : nullptr, ttab ? tI + (size_t)q * ttab : nullptr,
-                             a.spl ? a.spl + (size_t)(blockIdx.x * rpw + q) * a.spl_cap : nullptr, a.spl_cap);
+                             a.spl ? a.spl + (size_t)(bid * rpw + q) * a.spl_cap : nullptr, a.spl_cap);
             dq[q] = 0;
         }
         // Keep this barrier.  Without it (the run-owning lanes feeding the
@@ -399,7 +412,7 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a, int lg_rpw)
                 rsl[q0_io + e].write_stats(a.runstat, run0_io + e);
 }
 
-typedef void (*SparseFn)(GraphArgs, int);
+typedef void (*SparseFn)(GraphArgs, int, const GraphGroup *);
 
 template <typename S, int VEC, int LPS, bool HAS_H, bool UNIT, bool DAMP>
 static SparseFn sp_pick(bool jac, bool trackd)

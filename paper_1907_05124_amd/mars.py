@@ -52,7 +52,7 @@ class Result(C.Structure):
 
 
 EXPORTS = ["mars_create", "mars_create_csr", "mars_create_lattice", "mars_destroy", "mars_describe", "mars_solve",
-           "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_energy_noalloc", "mars_spectrum",
+           "mars_solve_ex", "mars_solve_async", "mars_solve_group_async", "mars_energy", "mars_energy_noalloc", "mars_spectrum",
            "mars_auto_temperatures", "mars_batch_create", "mars_batch_add", "mars_batch_step", "mars_batch_destroy", "mars_status_str",
            "mars_last_error"]
 
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
         L.mars_solve_ex.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp, i32,
                                     C.POINTER(Result), vp]
         L.mars_solve_async.argtypes = [vp, i32, C.POINTER(Schedule), u64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.mars_solve_group_async.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.mars_energy.argtypes = [vp, vp, i32, vp, vp]
         L.mars_energy_noalloc.argtypes = [vp, vp, i32, vp, vp]
         L.mars_spectrum.argtypes = [vp, i32, u64, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
@@ -94,7 +95,7 @@ def load(path: str = LIB_PATH):
         L.mars_last_error.argtypes = []
         L.mars_last_error.restype = C.c_char_p
         for f in ("mars_create", "mars_create_csr", "mars_create_lattice", "mars_describe", "mars_solve",
-                  "mars_solve_ex", "mars_solve_async", "mars_energy", "mars_energy_noalloc", "mars_spectrum",
+                  "mars_solve_ex", "mars_solve_async", "mars_solve_group_async", "mars_energy", "mars_energy_noalloc", "mars_spectrum",
                   "mars_auto_temperatures", "mars_batch_create", "mars_batch_add", "mars_batch_step"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -275,9 +276,43 @@ class Instance:
         return out
 
     @staticmethod
-    def read_result(result_buf) -> dict:
-        """Decode a pinned result buffer filled by solve_async (after the stream passed it)."""
-        raw = bytes(result_buf.cpu().numpy()[: C.sizeof(Result)])
+    def solve_group_async(members, result_buf, *, stream, want_energies=False, want_best=True) -> list:
+        """mars_solve_group_async: `members` is a list of (Instance, runs,
+        schedule, seed) lattice/sparse solves enqueued together on `stream`;
+        `result_buf` a pinned uint8 tensor of at least len(members) *
+        sizeof(Result) bytes (read_result(result_buf, i) decodes member i).
+        Returns each member's device outputs (valid once the stream has
+        passed the enqueued work)."""
+        import torch
+
+        n = len(members)
+        if result_buf.numel() < n * C.sizeof(Result):
+            raise ValueError("result_buf holds fewer than %d results" % n)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        outs = []
+        for inst, runs, _, _ in members:
+            o = {}
+            if want_energies:
+                o["energies"] = torch.empty(int(runs), dtype=torch.float64, device=dev)
+            if want_best:
+                o["best_spins"] = torch.empty(inst.N, dtype=torch.int8, device=dev)
+            outs.append(o)
+        handles = (C.c_void_p * n)(*[m[0]._h for m in members])
+        runs = (C.c_int32 * n)(*[int(m[1]) for m in members])
+        scheds = (Schedule * n)(*[make_schedule(m[2]) for m in members])
+        seeds = (C.c_uint64 * n)(*[int(m[3]) & (2**64 - 1) for m in members])
+        best = (C.c_void_p * n)(*[_ptr(o.get("best_spins")) for o in outs])
+        ens = (C.c_void_p * n)(*[_ptr(o.get("energies")) for o in outs])
+        _check(load().mars_solve_group_async(n, handles, runs, scheds, seeds, best, ens, result_buf.data_ptr(),
+                                             C.c_void_p(stream.cuda_stream)))
+        return outs
+
+    @staticmethod
+    def read_result(result_buf, index: int = 0) -> dict:
+        """Decode a pinned result buffer filled by solve_async (or member
+        `index` of solve_group_async), after the stream passed it."""
+        k = C.sizeof(Result)
+        raw = bytes(result_buf.cpu().numpy()[index * k: (index + 1) * k])
         return Result.from_buffer_copy(raw).as_dict()
 
     def energy_noalloc(self, spins, energies):

@@ -14,7 +14,10 @@ own (fewer 128 x 128 output tiles per update phase than the chip has compute
 units) join a batch instead (``mars_batch_*``): every update phase of all
 batch members is one launch, and members join and leave between sweeps.
 Larger requests run alone on the stream pool, where they fill the GPU
-anyway, and do not hold small members back to their pace.
+anyway, and do not hold small members back to their pace.  Sparse requests
+admitted in the same pass are enqueued together (``mars_solve_group_async``):
+those on the same instantiation of the LDS-resident solver share its launch,
+which fills the GPU with the workgroups of several small requests at once.
 
 Every solve is independent and deterministic (counter-based draws, fixed
 reduction orders), so a request's result is the same whether it runs alone
@@ -33,6 +36,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import inputs as I
+
+GROUP_MAX = 64  # solves per mars_solve_group_async call
+RESULT_BYTES = 256  # room for one mars_result in a pinned result buffer
 
 # ---------------------------------------------------------------------------
 # requests and footprints
@@ -217,7 +223,7 @@ class MarsServer:
     """Runs a stream of requests with continuous batching on the current GPU."""
 
     def __init__(self, hbm_budget: int | None = None, max_active: int = 8, n_streams: int = 4, batching: bool = True,
-                 batch_sweeps: int = 8):
+                 batch_sweeps: int = 8, grouping: bool = True):
         import torch
 
         from . import mars as M
@@ -234,6 +240,7 @@ class MarsServer:
         self.batching = batching
         self.batch_sweeps = int(batch_sweeps)
         self.batch_stream = torch.cuda.Stream() if batching else None
+        self.grouping = grouping
 
     def run(self, requests, time_scale: float = 1.0, verbose: bool = False, progress=None,
             progress_every_s: float = 30.0):
@@ -254,6 +261,7 @@ class MarsServer:
         done = []
         stream_load = [0] * len(self.streams)
         peak_running = peak_batch = 0
+        n_grouped = 0  # requests enqueued in groups of two or more
         t0 = time.perf_counter()
         last_report = t0
         try:
@@ -267,7 +275,10 @@ class MarsServer:
                 still = []
                 for job in running:
                     if job["event"] is not None and job["event"].query():
-                        res = M.Instance.read_result(job["buf"])
+                        if "group_buf" in job:
+                            res = M.Instance.read_result(job["group_buf"], job["group_index"])
+                        else:
+                            res = M.Instance.read_result(job["buf"])
                         best = job["outs"]["best_spins"].cpu().numpy()
                         fin = (time.perf_counter() - t0) / time_scale
                         done.append(Completion(job["req"].rid, res, best, job["req"].arrival, job["admitted"], fin,
@@ -301,6 +312,7 @@ class MarsServer:
                     room[cls] -= 1
                     return True
 
+                grouped = []  # sparse requests admitted in this pass: enqueued together
                 for req, fp in sched.admissible(now, accept):
                     inst = M.Instance.from_inputs(req.materialize())
                     buf = torch.empty(256, dtype=torch.uint8, pin_memory=True)
@@ -311,6 +323,8 @@ class MarsServer:
                             job["outs"] = batch.add(inst, req.runs, req.schedule, req.seed, req.rid, buf)
                         job["stream"] = -1
                         by_tag[req.rid] = job
+                    elif self.grouping and not req.dense:
+                        grouped.append(job)
                     else:
                         k = int(np.argmin(stream_load))
                         stream = self.streams[k]
@@ -322,8 +336,33 @@ class MarsServer:
                         stream_load[k] += 1
                     running.append(job)
                     if verbose:
-                        print("admit", req.rid, "N", req.N, "runs", req.runs, "stream", job["stream"], flush=True)
+                        print("admit", req.rid, "N", req.N, "runs", req.runs, "stream", job.get("stream"), flush=True)
                     progressed = True
+                # sparse requests admitted together share the solver's launches
+                # (mars_solve_group_async): one stream, one completion event
+                for g0 in range(0, len(grouped), GROUP_MAX):
+                    part = grouped[g0:g0 + GROUP_MAX]
+                    k = int(np.argmin(stream_load))
+                    stream = self.streams[k]
+                    if len(part) == 1:
+                        j = part[0]
+                        j["outs"] = j["inst"].solve_async(j["req"].runs, j["req"].schedule, j["req"].seed, j["buf"],
+                                                          stream=stream)
+                    else:
+                        n_grouped += len(part)
+                        gbuf = torch.empty(len(part) * RESULT_BYTES, dtype=torch.uint8, pin_memory=True)
+                        outs = M.Instance.solve_group_async(
+                            [(j["inst"], j["req"].runs, j["req"].schedule, j["req"].seed) for j in part], gbuf,
+                            stream=stream)
+                        for i, j in enumerate(part):
+                            j["outs"] = outs[i]
+                            j["group_buf"], j["group_index"] = gbuf, i
+                    ev = torch.cuda.Event()
+                    ev.record(stream)
+                    for j in part:
+                        j["event"] = ev
+                        j["stream"] = k
+                    stream_load[k] += len(part)
                 # advance the batch, keeping at most two steps queued ahead of the GPU
                 while inflight and inflight[0].query():
                     inflight.pop(0)
@@ -353,7 +392,7 @@ class MarsServer:
         lat = np.array([c.latency for c in done]) if done else np.zeros(1)
         updates = sum(int(c.result["spin_updates"]) for c in done)
         stats = {"requests": len(done), "rejected": len(sched.rejected), "makespan_s": makespan,
-                 "peak_concurrent": peak_running, "peak_batch": peak_batch,
+                 "peak_concurrent": peak_running, "peak_batch": peak_batch, "grouped_requests": n_grouped,
                  "spin_updates": updates, "spin_updates_per_s": updates / makespan if makespan > 0 else 0.0,
                  "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
                  "latency_p99_ms": float(np.percentile(lat, 99) * 1e3)}

@@ -9,8 +9,8 @@ from tests.gpu_common import announce, require_gpu, solve_summary
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("batching", [True, False])
-def test_served_results_equal_alone(batching):
+@pytest.mark.parametrize("batching,grouping", [(True, True), (False, False), (False, True)])
+def test_served_results_equal_alone(batching, grouping):
     require_gpu()
     from paper_1907_05124_amd import mars as M
     from paper_1907_05124_amd import serve as S
@@ -18,14 +18,18 @@ def test_served_results_equal_alone(batching):
     reqs = S.mixed_stream(16, rate=500.0, seed=5, n_lo=100, n_hi=1500, runs_lo=256, runs_hi=1024, levels=60)
     for r in reqs:
         r.instance = r.materialize()
-    announce("serve mixed", len(reqs), "batching", batching)
-    server = S.MarsServer(max_active=6, n_streams=4, batching=batching)
+    announce("serve mixed", len(reqs), "batching", batching, "grouping", grouping)
+    server = S.MarsServer(max_active=6, n_streams=4, batching=batching, grouping=grouping)
     done, stats = server.run(reqs)
     print(stats)
     assert stats["requests"] == len(reqs) and stats["rejected"] == 0
     assert stats["peak_concurrent"] >= 2
     if batching:
         assert stats["peak_batch"] >= 2
+    if grouping:
+        assert stats["grouped_requests"] >= 2
+    else:
+        assert stats["grouped_requests"] == 0
     for c, r in zip(done, reqs):
         assert c.rid == r.rid
         with M.Instance.from_inputs(r.instance) as g:
