@@ -261,7 +261,12 @@ static mars_status graph_solve_or_plan(const Instance &I, const GraphSolve &g, h
         for (int c = 0; c < I.ncolours; ++c)
             widest = std::max(widest, I.h_cls[2 * c + 1]);
     }
-    int Tq = std::min(1024 / (nq * lps), (widest + 63) / 64 * 64);
+    // MARS_SPARSE_THREADS=<64..1024, power of two> caps the workgroup (tuning)
+    int cap = 1024;
+    const int want_thr = env_int("MARS_SPARSE_THREADS", 0);
+    if (want_thr >= 64 && want_thr <= 1024 && (want_thr & (want_thr - 1)) == 0)
+        cap = want_thr;
+    int Tq = std::min(cap / (nq * lps), (widest + 63) / 64 * 64);
     Tq = std::max(Tq, std::max(1, 64 / (nq * lps)));
     if (plan) {
         e = plan_sparse_solve(a, (int)esz, rpw, Tq, vec, lps, jac, trackd, I.unit, plan);

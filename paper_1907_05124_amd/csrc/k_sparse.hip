@@ -21,19 +21,28 @@ hipError_t plan_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int v
         ++lg;
     const bool has_h = a.hhalf32 != nullptr;
     const bool damp = a.damping != 1.0;
-    SparseFn fn = nullptr;
-    if (lps > 1)
-        fn = sparse_split_kernel(esz, vec, lps, damp, has_h, unit, jac, trackd);
-    else if (esz == 8)
+    SparseFn fn = nullptr, gfn = nullptr;
+    if (lps > 1) {
+        fn = sparse_split_kernel(esz, vec, lps, damp, has_h, unit, jac, trackd, false);
+        gfn = sparse_split_kernel(esz, vec, lps, damp, has_h, unit, jac, trackd, true);
+    } else if (esz == 8) {
         fn = sp_pick_d<double, 1, 1>(damp, has_h, unit, jac, trackd);
-    else if (esz == 4)
+        gfn = sp_pick_group<double, 1, 1>(damp, has_h, unit, jac, trackd);
+    } else if (esz == 4) {
         fn = vec == 4   ? sp_pick_d<float, 4, 1>(damp, has_h, unit, jac, trackd)
              : vec == 2 ? sp_pick_d<float, 2, 1>(damp, has_h, unit, jac, trackd)
                         : sp_pick_d<float, 1, 1>(damp, has_h, unit, jac, trackd);
-    else
+        gfn = vec == 4   ? sp_pick_group<float, 4, 1>(damp, has_h, unit, jac, trackd)
+              : vec == 2 ? sp_pick_group<float, 2, 1>(damp, has_h, unit, jac, trackd)
+                         : sp_pick_group<float, 1, 1>(damp, has_h, unit, jac, trackd);
+    } else {
         fn = vec == 4   ? sp_pick_d<_Float16, 4, 1>(damp, has_h, unit, jac, trackd)
              : vec == 2 ? sp_pick_d<_Float16, 2, 1>(damp, has_h, unit, jac, trackd)
                         : sp_pick_d<_Float16, 1, 1>(damp, has_h, unit, jac, trackd);
+        gfn = vec == 4   ? sp_pick_group<_Float16, 4, 1>(damp, has_h, unit, jac, trackd)
+              : vec == 2 ? sp_pick_group<_Float16, 2, 1>(damp, has_h, unit, jac, trackd)
+                         : sp_pick_group<_Float16, 1, 1>(damp, has_h, unit, jac, trackd);
+    }
     if (!fn)
         return hipErrorInvalidValue;
     const size_t rows = (size_t)a.nslot + 1;
@@ -43,6 +52,7 @@ hipError_t plan_sparse_solve(const GraphArgs &a, int esz, int rpw, int Tq, int v
     if (threads > 1024 || Tq < 1 || threads % 64 != 0)
         return hipErrorInvalidConfiguration;
     plan->fn = reinterpret_cast<const void *>(fn);
+    plan->gfn = reinterpret_cast<const void *>(gfn);
     plan->args = a;
     plan->args.ttab = level_table_fit(a.ttab, rpw, base_lds, threads, (a.R + rpw - 1) / rpw);
     plan->lg = lg;
@@ -63,16 +73,18 @@ hipError_t launch_sparse_plans(const SparsePlan *plans, int n, GraphGroup *host_
         return hipErrorInvalidValue;
     int blocks = 0, threads = 0;
     size_t lds = 0;
+    // one solve: its own kernel; several: the group instantiation they share
+    const void *kfn = n == 1 ? plans[0].fn : plans[0].gfn;
     for (int k = 0; k < n; ++k) {
-        if (plans[k].fn != plans[0].fn)
+        if (!kfn || (n > 1 && plans[k].gfn != kfn))
             return hipErrorInvalidValue;
         blocks += plans[k].blocks;
         threads = std::max(threads, plans[k].threads);
         lds = std::max(lds, plans[k].lds);
     }
-    SparseFn fn = reinterpret_cast<SparseFn>(const_cast<void *>(plans[0].fn));
+    SparseFn fn = reinterpret_cast<SparseFn>(const_cast<void *>(kfn));
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(plans[0].fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess)
             return e;
     }

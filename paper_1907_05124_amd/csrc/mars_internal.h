@@ -370,11 +370,12 @@ struct GraphGroup {
     GraphArgs args[GRAPH_GROUP_MAX];
 };
 // How one sparse solve launches the LDS-resident solver: the kernel
-// (instantiation), its arguments, and the launch shape.  Solves whose kernels
-// agree can share one launch (the block shape is the largest of theirs: the
+// (instantiation), its arguments, and the launch shape.  Solves whose group
+// instantiations agree can share one launch (the block shape is the largest of theirs: the
 // kernel derives its slots in flight from it; the LDS size the largest).
 struct SparsePlan {
-    const void *fn = nullptr;
+    const void *fn = nullptr;   // the kernel of the solve alone
+    const void *gfn = nullptr;  // its group instantiation, or null (then it launches alone)
     GraphArgs args;
     int lg = 0, blocks = 0, threads = 0;
     size_t lds = 0;

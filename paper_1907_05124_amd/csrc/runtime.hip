@@ -1510,9 +1510,10 @@ mars_status mars_solve_group_async(int32_t count, mars_instance *const *insts, c
     for (int i = 0; i < count; ++i) {
         if (!P[i].fn || launched[i])
             continue;
-        std::vector<SparsePlan> same;
-        for (int j = i; j < count; ++j)
-            if (!launched[j] && P[j].fn == P[i].fn) {
+        std::vector<SparsePlan> same{P[i]};
+        launched[i] = true;
+        for (int j = i + 1; j < count && P[i].gfn; ++j)
+            if (!launched[j] && P[j].fn && P[j].gfn == P[i].gfn) {
                 same.push_back(P[j]);
                 launched[j] = true;
             }

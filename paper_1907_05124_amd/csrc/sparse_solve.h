@@ -90,23 +90,12 @@ __device__ __forceinline__ void split_reduce(const float (&phi)[VEC], float (&ow
     }
 }
 
+// The anneal of one block of runs: a = the solve's arguments, 2^lg_rpw runs
+// per workgroup, bid = the block's index within the solve.
 template <typename S, int VEC, int LPS, bool JAC, bool TRACKD, bool HAS_H, bool UNIT, bool DAMP>
-__global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a_one, int lg_one, const GraphGroup *grp)
+__device__ __forceinline__ void sparse_solve_block(const GraphArgs &a, int lg_rpw, int bid)
 {
     typedef typename LStore<S>::C C;
-    // one instance (grp null), or the instances of a group, each with its own
-    // consecutive blocks: the block finds its instance and its index there
-    int bid = blockIdx.x;
-    int lg_rpw = lg_one;
-    GraphArgs a = a_one;
-    if (grp) {
-        int k = 0;
-        while (k + 1 < grp->count && bid >= grp->first[k + 1])
-            ++k;
-        bid -= grp->first[k];
-        lg_rpw = grp->lg[k];
-        a = grp->args[k];
-    }
     static_assert(LPS == 1 || (sizeof(C) == 4 && VEC % LPS == 0), "lane split needs fp32 fields and LPS | VEC");
     constexpr int OWN = VEC / LPS;  // runs each lane updates
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
@@ -412,16 +401,34 @@ __global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a_one, int lg_o
                 rsl[q0_io + e].write_stats(a.runstat, run0_io + e);
 }
 
+// One solve (GROUP false: a_one, lg_one, the block index), or the solves of
+// a group (GROUP true: each owns consecutive blocks; a block finds its solve
+// in the descriptor).  The two are separate instantiations so that a single
+// solve reads its arguments straight from the kernel arguments.
+template <typename S, int VEC, int LPS, bool JAC, bool TRACKD, bool HAS_H, bool UNIT, bool DAMP, bool GROUP>
+__global__ __launch_bounds__(1024) void k_sparse_solve(GraphArgs a_one, int lg_one, const GraphGroup *grp)
+{
+    if constexpr (!GROUP) {
+        sparse_solve_block<S, VEC, LPS, JAC, TRACKD, HAS_H, UNIT, DAMP>(a_one, lg_one, blockIdx.x);
+    } else {
+        int k = 0;
+        while (k + 1 < grp->count && (int)blockIdx.x >= grp->first[k + 1])
+            ++k;
+        sparse_solve_block<S, VEC, LPS, JAC, TRACKD, HAS_H, UNIT, DAMP>(grp->args[k], grp->lg[k],
+                                                                         (int)blockIdx.x - grp->first[k]);
+    }
+}
+
 typedef void (*SparseFn)(GraphArgs, int, const GraphGroup *);
 
 template <typename S, int VEC, int LPS, bool HAS_H, bool UNIT, bool DAMP>
 static SparseFn sp_pick(bool jac, bool trackd)
 {
     if (jac)
-        return trackd ? k_sparse_solve<S, VEC, LPS, true, true, HAS_H, UNIT, DAMP>
-                      : k_sparse_solve<S, VEC, LPS, true, false, HAS_H, UNIT, DAMP>;
-    return trackd ? k_sparse_solve<S, VEC, LPS, false, true, HAS_H, UNIT, DAMP>
-                  : k_sparse_solve<S, VEC, LPS, false, false, HAS_H, UNIT, DAMP>;
+        return trackd ? k_sparse_solve<S, VEC, LPS, true, true, HAS_H, UNIT, DAMP, false>
+                      : k_sparse_solve<S, VEC, LPS, true, false, HAS_H, UNIT, DAMP, false>;
+    return trackd ? k_sparse_solve<S, VEC, LPS, false, true, HAS_H, UNIT, DAMP, false>
+                  : k_sparse_solve<S, VEC, LPS, false, false, HAS_H, UNIT, DAMP, false>;
 }
 
 template <typename S, int VEC, int LPS, bool DAMP>
@@ -441,9 +448,29 @@ static SparseFn sp_pick_d(bool damp, bool has_h, bool unit, bool jac, bool track
                 : sp_pick_hu<S, VEC, LPS, false>(has_h, unit, jac, trackd);
 }
 
+// group instantiations: the phased, undamped update (what a serving stream
+// runs), with or without the paper's stopping rule, field and +-1 weights;
+// null otherwise (such solves launch alone)
+template <typename S, int VEC, int LPS>
+static SparseFn sp_pick_group(bool damp, bool has_h, bool unit, bool jac, bool trackd)
+{
+    if (damp || jac)
+        return nullptr;
+    if (has_h)
+        return unit ? (trackd ? k_sparse_solve<S, VEC, LPS, false, true, true, true, false, true>
+                              : k_sparse_solve<S, VEC, LPS, false, false, true, true, false, true>)
+                    : (trackd ? k_sparse_solve<S, VEC, LPS, false, true, true, false, false, true>
+                              : k_sparse_solve<S, VEC, LPS, false, false, true, false, false, true>);
+    return unit ? (trackd ? k_sparse_solve<S, VEC, LPS, false, true, false, true, false, true>
+                          : k_sparse_solve<S, VEC, LPS, false, false, false, true, false, true>)
+                : (trackd ? k_sparse_solve<S, VEC, LPS, false, true, false, false, false, true>
+                          : k_sparse_solve<S, VEC, LPS, false, false, false, false, false, true>);
+}
+
 // the split kernels (LPS = 2 or 4; fp32 and fp16 storage, four runs per
 // lane group), instantiated in their own translation unit; null for other
-// combinations
-SparseFn sparse_split_kernel(int esz, int vec, int lps, bool damp, bool has_h, bool unit, bool jac, bool trackd);
+// combinations (group: the group instantiation, or null)
+SparseFn sparse_split_kernel(int esz, int vec, int lps, bool damp, bool has_h, bool unit, bool jac, bool trackd,
+                             bool group);
 
 }  // namespace mars
