@@ -167,10 +167,11 @@ mars_status mars_describe(const mars_instance *inst, const mars_schedule *sched,
  * slots times 8, 4 or 2 bytes in fp64, fp32, fp16); a sparse instance
  * beyond that keeps its state in device memory (a workspace of
  * (slots + 1) x runs values; about a quarter of the LDS path's throughput
- * at equal size), a lattice beyond it is refused.  Errors: MARS_E_ARG (runs < 1, bad
- * schedule), MARS_E_UNSUPPORTED (precision not available for this
- * instance type, or a lattice whose one-run state does not fit in LDS),
- * MARS_E_OOM, MARS_E_DEVICE. */
+ * at equal size), and so does a lattice, over sparse encodings of its
+ * couplings built on its first such solve (up to 2^24 sites).  Errors:
+ * MARS_E_ARG (runs < 1, bad schedule), MARS_E_UNSUPPORTED (precision not
+ * available for this instance type, or a lattice beyond LDS with 2^24 sites
+ * or more), MARS_E_OOM, MARS_E_DEVICE. */
 mars_status mars_solve(mars_instance *inst, int32_t runs, const mars_schedule *sched, uint64_t seed,
                        int8_t *best_spins, double *energies, mars_result *res);
 

@@ -52,11 +52,15 @@ static constexpr size_t kLdsCap = 160 * 1024 - 1024;
 // sizes the oracle handles)
 static bool sparse_global(const Instance &I, const mars_schedule &sc)
 {
-    if (I.kind == KIND_LATTICE)
-        return false;
     const size_t esz = graph_esz(sc.precision);
-    const size_t per_run = ((size_t)I.nslot + 1) * esz * (sc.update == MARS_JACOBI ? 2 : 1);
+    const size_t rows = I.kind == KIND_LATTICE ? (size_t)I.N : (size_t)I.nslot + 1;
+    const size_t per_run = rows * esz * (sc.update == MARS_JACOBI ? 2 : 1);
     return per_run + 16 + RUN_AREA_MAX > kLdsCap || env_int("MARS_GRAPH_GLOBAL", 0) == 1;
+}
+
+bool graph_uses_global(const Instance &I, const mars_schedule &sc)
+{
+    return graph_esz(sc.precision) != 0 && sparse_global(I, sc);
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -111,11 +115,11 @@ static mars_status graph_solve_or_plan(const Instance &I, const GraphSolve &g, h
     const size_t rows = lat ? (size_t)N : (size_t)I.nslot + 1;
     const size_t per_run = rows * esz * (jac ? 2 : 1);
     const size_t lds_cap = kLdsCap;
-    const bool global = !lat && sparse_global(I, sc);
+    const bool global = sparse_global(I, sc);
     if (!global && per_run + 16 + RUN_AREA_MAX > lds_cap)
-        return set_error(MARS_E_UNSUPPORTED, "the state of one lattice run does not fit in LDS (N too large)");
-    if (global && !g.gscratch)
-        return set_error(MARS_E_ARG, "the sparse solver beyond LDS needs its device memory");
+        return set_error(MARS_E_UNSUPPORTED, "the state of one run does not fit in LDS");
+    if (global && (!g.gscratch || (lat && !I.lat_sell)))
+        return set_error(MARS_E_ARG, "the sparse solver beyond LDS needs its device memory and encodings");
     // runs per workgroup: as many as fit the LDS budget while at least one
     // workgroup per CU (256) remains; more runs per workgroup give each phase
     // more independent (spin, run) items per barrier
@@ -198,6 +202,9 @@ static mars_status graph_solve_or_plan(const Instance &I, const GraphSolve &g, h
         unsigned char *base = static_cast<unsigned char *>(g.gscratch);
         SparseGlobalArgs ga;
         ga.a = a;
+        // the field by slot (for a lattice: over its sparse encodings)
+        ga.a.hhalf32 = I.has_h ? I.hperm : nullptr;
+        ga.a.hhalf64 = I.has_h ? I.hperm64 : nullptr;
         ga.m = base + L.m;
         ga.m2 = base + L.m2;
         ga.ldr = L.ldr;

@@ -136,6 +136,11 @@ struct Instance {
     bool done_recorded = false;
     bool in_batch = false;  // owned by a batch until its member finishes
     double tick_s = 0.0;    // seconds per tick of the device's constant-rate clock
+    // lattice: the bonds and field as given (host), from which the sparse
+    // encodings are built when a solve needs the solver beyond LDS
+    std::vector<int8_t> lat_bond;
+    std::vector<float> lat_h;
+    bool lat_sell = false;
     // descriptor of a shared sparse launch this instance led: host copy (kept
     // until its copy to the device has run, grp_event) and device copy
     std::vector<unsigned char> grp_host;
@@ -313,8 +318,12 @@ struct SparsePlan;
 // planned (*plan, plan->fn set) instead of enqueued, for a shared launch;
 // other solves are enqueued (plan->fn null)
 mars_status plan_graph_solve(const Instance &I, const GraphSolve &g, hipStream_t s, SparsePlan *plan);
-// bytes of device memory the solve needs for a sparse instance whose one-run
-// state does not fit in LDS (0: the LDS-resident solver takes it)
+// whether a lattice/sparse solve runs with its state in device memory (one
+// run's state does not fit in LDS, or MARS_GRAPH_GLOBAL=1); a lattice then
+// runs on the sparse solver over its sparse encodings (built on first use)
+bool graph_uses_global(const Instance &I, const mars_schedule &sc);
+// bytes of device memory that solve needs (0: the LDS-resident solvers take
+// it); for a lattice the sparse encodings must exist
 size_t graph_global_bytes(const Instance &I, const mars_schedule &sc, int R);
 
 // kernel arguments of the lattice / sparse solvers

@@ -378,58 +378,17 @@ static mars_status create_dense(const float *J, const float *h, int N, Instance 
     return MARS_OK;
 }
 
-static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, const int8_t *val, const float *h,
-                              Instance *I)
+// Solver encodings of a symmetric sparse coupling matrix given as CSR: the
+// greedy colouring (update phases), the sliced-ELL table and the field by
+// slot (ncolours, nslot, unit, h_cls, perm, sl_meta, colsell, cls, hperm,
+// hperm64 of the instance).  Inputs are valid (checked by the caller).
+static mars_status build_sell(Instance *I, int N, const int32_t *rowptr, const int32_t *col, const int8_t *val,
+                              const float *h)
 {
-    I->kind = KIND_CSR;
-    I->N = N;
-    if (rowptr[0] != 0)
-        return set_error(MARS_E_ARG, "rowptr[0] must be 0");
-    for (int i = 0; i < N; ++i)
-        if (rowptr[i + 1] < rowptr[i])
-            return set_error(MARS_E_ARG, "rowptr must be non-decreasing");
-    const long long nnz = rowptr[N];
-    if (nnz > 0 && (!col || !val))
-        return set_error(MARS_E_ARG, "col and val are required when nnz > 0");
-    if (N >= (1 << 24))
-        return set_error(MARS_E_UNSUPPORTED, "sparse instances are limited to N < 2^24");
-    FixInfo fx;
+    mars_status st;
     int maxdeg = 0;
-    double wsum = 0.0;
-    for (int i = 0; i < N; ++i) {
+    for (int i = 0; i < N; ++i)
         maxdeg = std::max(maxdeg, rowptr[i + 1] - rowptr[i]);
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            int j = col[k];
-            if (j < 0 || j >= N)
-                return set_error(MARS_E_ARG, "column index out of range");
-            if (k > rowptr[i] && col[k - 1] >= j)
-                return set_error(MARS_E_ARG, "columns must be strictly increasing within a row");
-            if (j == i)
-                return set_error(MARS_E_DIAGONAL, "self loop in CSR");
-            if (val[k] == 0)
-                return set_error(MARS_E_ARG, "stored values must be nonzero");
-            // the mirror entry (j, i) must exist with the same value
-            const int32_t *b = col + rowptr[j], *e = col + rowptr[j + 1];
-            const int32_t *f = std::lower_bound(b, e, i);
-            if (f == e || *f != i || val[rowptr[j] + (f - b)] != val[k])
-                return set_error(MARS_E_ASYMMETRIC, "CSR couplings are not symmetric");
-            fx.add((float)val[k]);
-            wsum -= (double)val[k];
-        }
-    }
-    mars_status st = check_h(h, N, fx);
-    if (st != MARS_OK)
-        return st;
-    I->emin = fx.any ? std::min(0, fx.emin) : 0;
-    I->maxdeg = maxdeg;
-    I->wsum = wsum;
-    I->nnz = (int)nnz;
-    {
-        // energy accumulates in 64 bits: N * (maxdeg * 128 + max|h|) in units of 2^emin
-        const int bits = (fx.any ? fx.emax : 0) - I->emin + ceil_log2((long long)maxdeg + 2) + 1;
-        if (bits + ceil_log2((long long)N + 1) + 1 > 62)
-            return set_error(MARS_E_RANGE, "exact energy would overflow 64-bit accumulation");
-    }
     // greedy colouring in index order: colour(v) = smallest colour not used by
     // neighbours u < v; each colour class is one update phase
     std::vector<int32_t> colour((size_t)N, 0);
@@ -459,10 +418,6 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
             pvert[fill[colour[v]]++] = v;
     }
     I->ncolours = ncol;
-    // CSR copy for exact energies (original labels)
-    std::vector<uint32_t> cv((size_t)std::max<long long>(nnz, 1));
-    for (long long k = 0; k < nnz; ++k)
-        cv[k] = ((uint32_t)col[k] << 8) | (uint32_t)(uint8_t)val[k];
     // sliced-ELL copy for the solver: classes in colour order, each sorted by
     // degree (descending, ties by index) and padded to whole slices, so that
     // the SELL_H vertices of a slice have similar degrees and the threads of a
@@ -526,10 +481,6 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
     I->nslot = nslot;
     I->unit = unit;
     I->h_cls = cls;
-    if ((st = dev_alloc(&I->rowptr, (size_t)N + 1)) != MARS_OK)
-        return st;
-    if ((st = dev_alloc(&I->colval, cv.size())) != MARS_OK)
-        return st;
     if ((st = dev_alloc(&I->perm, perm.size())) != MARS_OK)
         return st;
     if ((st = dev_alloc(&I->sl_meta, meta.size())) != MARS_OK)
@@ -539,8 +490,6 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
     if ((st = dev_alloc(&I->cls, cls.size())) != MARS_OK)
         return st;
     hipStream_t s = I->own_stream;
-    MARS_HIP(hipMemcpyAsync(I->rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s));
-    MARS_HIP(hipMemcpyAsync(I->colval, cv.data(), sizeof(uint32_t) * cv.size(), hipMemcpyHostToDevice, s));
     MARS_HIP(hipMemcpyAsync(I->perm, perm.data(), sizeof(int32_t) * perm.size(), hipMemcpyHostToDevice, s));
     MARS_HIP(hipMemcpyAsync(I->sl_meta, meta.data(), sizeof(int32_t) * meta.size(), hipMemcpyHostToDevice, s));
     MARS_HIP(hipMemcpyAsync(I->colsell, cs.data(), sizeof(uint32_t) * cs.size(), hipMemcpyHostToDevice, s));
@@ -567,6 +516,74 @@ static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, 
         }
     }
     MARS_HIP(hipStreamSynchronize(s));
+    return MARS_OK;
+}
+
+static mars_status create_csr(int N, const int32_t *rowptr, const int32_t *col, const int8_t *val, const float *h,
+                              Instance *I)
+{
+    I->kind = KIND_CSR;
+    I->N = N;
+    if (rowptr[0] != 0)
+        return set_error(MARS_E_ARG, "rowptr[0] must be 0");
+    for (int i = 0; i < N; ++i)
+        if (rowptr[i + 1] < rowptr[i])
+            return set_error(MARS_E_ARG, "rowptr must be non-decreasing");
+    const long long nnz = rowptr[N];
+    if (nnz > 0 && (!col || !val))
+        return set_error(MARS_E_ARG, "col and val are required when nnz > 0");
+    if (N >= (1 << 24))
+        return set_error(MARS_E_UNSUPPORTED, "sparse instances are limited to N < 2^24");
+    FixInfo fx;
+    int maxdeg = 0;
+    double wsum = 0.0;
+    for (int i = 0; i < N; ++i) {
+        maxdeg = std::max(maxdeg, rowptr[i + 1] - rowptr[i]);
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int j = col[k];
+            if (j < 0 || j >= N)
+                return set_error(MARS_E_ARG, "column index out of range");
+            if (k > rowptr[i] && col[k - 1] >= j)
+                return set_error(MARS_E_ARG, "columns must be strictly increasing within a row");
+            if (j == i)
+                return set_error(MARS_E_DIAGONAL, "self loop in CSR");
+            if (val[k] == 0)
+                return set_error(MARS_E_ARG, "stored values must be nonzero");
+            // the mirror entry (j, i) must exist with the same value
+            const int32_t *b = col + rowptr[j], *e = col + rowptr[j + 1];
+            const int32_t *f = std::lower_bound(b, e, i);
+            if (f == e || *f != i || val[rowptr[j] + (f - b)] != val[k])
+                return set_error(MARS_E_ASYMMETRIC, "CSR couplings are not symmetric");
+            fx.add((float)val[k]);
+            wsum -= (double)val[k];
+        }
+    }
+    mars_status st = check_h(h, N, fx);
+    if (st != MARS_OK)
+        return st;
+    I->emin = fx.any ? std::min(0, fx.emin) : 0;
+    I->maxdeg = maxdeg;
+    I->wsum = wsum;
+    I->nnz = (int)nnz;
+    {
+        // energy accumulates in 64 bits: N * (maxdeg * 128 + max|h|) in units of 2^emin
+        const int bits = (fx.any ? fx.emax : 0) - I->emin + ceil_log2((long long)maxdeg + 2) + 1;
+        if (bits + ceil_log2((long long)N + 1) + 1 > 62)
+            return set_error(MARS_E_RANGE, "exact energy would overflow 64-bit accumulation");
+    }
+    // CSR copy for exact energies (original labels)
+    std::vector<uint32_t> cv((size_t)std::max<long long>(nnz, 1));
+    for (long long k = 0; k < nnz; ++k)
+        cv[k] = ((uint32_t)col[k] << 8) | (uint32_t)(uint8_t)val[k];
+    if ((st = dev_alloc(&I->rowptr, (size_t)N + 1)) != MARS_OK)
+        return st;
+    if ((st = dev_alloc(&I->colval, cv.size())) != MARS_OK)
+        return st;
+    MARS_HIP(hipMemcpyAsync(I->rowptr, rowptr, sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, I->own_stream));
+    MARS_HIP(hipMemcpyAsync(I->colval, cv.data(), sizeof(uint32_t) * cv.size(), hipMemcpyHostToDevice,
+                            I->own_stream));
+    if ((st = build_sell(I, N, rowptr, col, val, h)) != MARS_OK)
+        return st;
     return upload_h(I, h, N);
 }
 
@@ -646,7 +663,58 @@ static mars_status create_lattice(int dim, const int32_t *L, const int8_t *bond,
     MARS_HIP(hipMemcpyAsync(I->bondsgn, sgn.data(), (size_t)2 * N * sizeof(uint32_t), hipMemcpyHostToDevice,
                             I->own_stream));
     MARS_HIP(hipStreamSynchronize(I->own_stream));
+    // the bonds and field as given, for the sparse encodings of a solve
+    // beyond LDS (built on first use)
+    I->lat_bond.assign(bond, bond + (size_t)dim * N);
+    if (h)
+        I->lat_h.assign(h, h + N);
     return upload_h(I, h, (int)N);
+}
+
+// The sparse encodings of a lattice (its couplings as a symmetric CSR matrix:
+// site v couples to v + e_a with bond[a N + v] and to v - e_a with
+// bond[a N + (v - e_a)], periodic), for the solver beyond LDS.  Greedy
+// colouring in index order gives the checkerboard (every site but 0 has an
+// earlier neighbour, of the other parity), class 0 the even sites, as the
+// lattice solver's phases.
+static mars_status lattice_sell(Instance *I)
+{
+    if (I->lat_sell)
+        return MARS_OK;
+    const int dim = I->dim, N = I->N;
+    if (N >= (1 << 24))
+        return set_error(MARS_E_UNSUPPORTED, "lattices beyond LDS are limited to fewer than 2^24 sites");
+    const int L0 = I->L[0], L1 = I->L[1], L2 = dim == 3 ? I->L[2] : 1;
+    std::vector<int32_t> rowptr((size_t)N + 1), col((size_t)2 * dim * N);
+    std::vector<int8_t> val((size_t)2 * dim * N);
+    const int8_t *bond = I->lat_bond.data();
+    for (int v = 0; v < N; ++v) {
+        const int x = v % L0, y = (v / L0) % L1, z = v / (L0 * L1);
+        const int step[3] = {1, L0, L0 * L1};
+        const int coord[3] = {x, y, z}, len[3] = {L0, L1, L2};
+        std::pair<int32_t, int8_t> nb[6];
+        int n = 0;
+        for (int a = 0; a < dim; ++a) {
+            const int up = v + ((coord[a] + 1) % len[a] - coord[a]) * step[a];
+            const int dn = v + ((coord[a] + len[a] - 1) % len[a] - coord[a]) * step[a];
+            nb[n++] = {up, bond[(size_t)a * N + v]};
+            nb[n++] = {dn, bond[(size_t)a * N + dn]};
+        }
+        std::sort(nb, nb + n);
+        rowptr[v] = 2 * dim * v;
+        for (int k = 0; k < n; ++k) {
+            col[(size_t)2 * dim * v + k] = nb[k].first;
+            val[(size_t)2 * dim * v + k] = nb[k].second;
+        }
+    }
+    rowptr[N] = 2 * dim * N;
+    mars_status st = build_sell(I, N, rowptr.data(), col.data(), val.data(), I->lat_h.empty() ? nullptr : I->lat_h.data());
+    if (st != MARS_OK)
+        return st;
+    if (I->ncolours != 2)
+        return set_error(MARS_E_DEVICE, "lattice encodings: the colouring is not the checkerboard");
+    I->lat_sell = true;
+    return MARS_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -965,6 +1033,8 @@ static mars_status graph_pre(Instance *I, int R, const mars_schedule &sc, uint64
     g->runstat = (int64_t *)w.runstat.p;
     g->spl = spl;
     g->spl_cap = spl_cap;
+    if (I->kind == KIND_LATTICE && graph_uses_global(*I, sc) && (st = lattice_sell(I)) != MARS_OK)
+        return st;
     const size_t gbytes = graph_global_bytes(*I, sc, R);
     if (gbytes) {
         if ((st = ensure(w.gstate, gbytes)) != MARS_OK)

@@ -1,6 +1,7 @@
 """Parity of the sparse solver with its state in device memory (instances
 whose one-run state exceeds LDS; forced with MARS_GRAPH_GLOBAL=1 at sizes the
-oracle handles) against the CPU oracle, through the C ABI."""
+oracle handles) against the CPU oracle, through the C ABI.  Lattices take the
+same path over their sparse encodings."""
 import numpy as np
 import pytest
 
@@ -13,6 +14,7 @@ from tests.test_gpu_graph import CASES, _decided_spins_agree, _mars, _rel_sched
 pytestmark = pytest.mark.gpu
 
 SPARSE = ["er_pm1", "er_unit", "er_field", "er_dense_isolated", "er_int8", "er_int8_dense"]
+LATTICE = ["ea2d_16", "ea2d_6x4", "ea3d_8", "ea3d_4x6x8", "lat_field", "lat3d_field"]
 
 
 @pytest.fixture
@@ -22,7 +24,7 @@ def forced(monkeypatch):
     monkeypatch.delenv("MARS_SPARSE_LPS", raising=False)
 
 
-@pytest.mark.parametrize("case", SPARSE)
+@pytest.mark.parametrize("case", SPARSE + LATTICE)
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-9)])
 @pytest.mark.parametrize("R", [7, 1031])
 def test_global_one_level(case, precision, tol, R, forced):
@@ -40,7 +42,7 @@ def test_global_one_level(case, precision, tol, R, forced):
     assert out["result"]["sweeps_executed"] == R
 
 
-@pytest.mark.parametrize("case", ["er_pm1", "er_field", "er_dense_isolated"])
+@pytest.mark.parametrize("case", ["er_pm1", "er_field", "er_dense_isolated", "ea3d_8", "lat_field"])
 @pytest.mark.parametrize("update", ["phased", "jacobi"])
 def test_global_damped_and_synchronous(case, update, forced):
     """Damped (g = 0.5) phased and synchronous updates, one fp32 level."""
@@ -56,7 +58,7 @@ def test_global_damped_and_synchronous(case, update, forced):
     assert err <= 1e-5, err
 
 
-@pytest.mark.parametrize("case", ["er_pm1", "er_field", "er_int8_dense"])
+@pytest.mark.parametrize("case", ["er_pm1", "er_field", "er_int8_dense", "ea2d_16", "ea3d_8", "lat_field"])
 @pytest.mark.parametrize("precision,levels", [("fp64", 300), ("fp32", 300)])
 def test_global_anneal(case, precision, levels, forced):
     """Whole geometric anneal: every well-conditioned run (the rule of
@@ -80,13 +82,13 @@ def test_global_anneal(case, precision, levels, forced):
     assert np.array_equal(E[same], ref["energy"][same])
 
 
-@pytest.mark.parametrize("case", ["er_field", "er_int8_dense"])
+@pytest.mark.parametrize("case", ["er_field", "er_int8_dense", "ea3d_8", "lat3d_field"])
 def test_global_fp16_storage(case, forced):
     """fp16 storage: the bound of test_one_level_fp16_storage."""
     TG.test_one_level_fp16_storage(case, 1031)
 
 
-@pytest.mark.parametrize("case", ["er_field", "er_dense_isolated"])
+@pytest.mark.parametrize("case", ["er_field", "er_dense_isolated", "ea2d_16", "ea3d_8"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_global_paper_schedule_replay(case, precision, forced):
     """The paper's scheduler (linear decrement, sweeps until d < d_min): the
@@ -155,3 +157,52 @@ def test_beyond_lds_sampled(monkeypatch):
                                label="ER N=48000 runs %d..%d" % (r0, r0 + n - 1))
         _decided_spins_agree(S[r0:r0 + n], m[:, r0:r0 + n], ref, 1e-5)
     assert excl / 17 <= 0.1
+
+
+def test_lattice_global_matches_lds_solver(monkeypatch):
+    """A 3D lattice through both solvers, fp64, the paper's scheduler: the
+    same per-level sweep counts on at least 90 % of the runs, and there final
+    magnetisations within the fp64 bar 1e-9 (the two sum a site's six terms
+    in different orders)."""
+    M = _mars()
+    inst = CASES["ea3d_8"]()
+    s = I.field_scale(inst)
+    sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=1.5 * s, c_step=0.1 * s, max_sweeps=1000, d_min=1e-4,
+                     precision="fp64")
+    R = 300
+    announce("lattice global vs LDS", R)
+    outs = []
+    for forced_global in ("0", "1"):
+        monkeypatch.setenv("MARS_GRAPH_GLOBAL", forced_global)
+        with M.Instance.from_inputs(inst) as g:
+            outs.append(g.solve_ex(R, sch, 5, want_m=True, levels_cap=64))
+    a, b = outs
+    spl_a, spl_b = a["sweeps_per_level"].cpu().numpy(), b["sweeps_per_level"].cpu().numpy()
+    same = np.all(spl_a == spl_b, axis=1)
+    assert np.mean(same) >= 0.9, np.mean(same)
+    assert np.max(np.abs(a["m"].cpu().numpy() - b["m"].cpu().numpy())[:, same]) <= 1e-9
+
+
+def test_lattice_beyond_lds_sampled(monkeypatch):
+    """A 3D lattice whose one-run fp64 state exceeds LDS (28^3 sites, 172 KB
+    per run) takes the device-memory path without being forced: 16 sampled
+    runs of a 128-run anneal within 1e-9 of the oracle on every
+    well-conditioned run (at most 10 % excluded), decided spins equal."""
+    monkeypatch.delenv("MARS_GRAPH_GLOBAL", raising=False)
+    M = _mars()
+    require_gpu()
+    inst = I.lattice_instance((28, 28, 28), 5)
+    sch = _rel_sched(inst, precision="fp64", steps=60)
+    R = 128
+    announce("lattice beyond LDS", inst.N, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 9, want_m=True, want_spins=True)
+    m = out["m"].cpu().numpy()
+    S = out["spins"].cpu().numpy()
+    excl = 0.0
+    for r0 in (0, 120):
+        ref = O.solve(inst, R, sch, 9, run_begin=r0, run_count=8)
+        excl += 8 * c16_parity(m[:, r0:r0 + 8], inst, R, sch, 9, ref, "fp64", run_begin=r0, max_excluded=1.0,
+                               label="3D L=28 fp64 runs %d..%d" % (r0, r0 + 7))
+        _decided_spins_agree(S[r0:r0 + 8], m[:, r0:r0 + 8], ref, 1e-9)
+    assert excl / 16 <= 0.1
