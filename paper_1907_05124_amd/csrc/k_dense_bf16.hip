@@ -202,25 +202,38 @@ hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipSt
     Bf16BatchArgs a;
     a.level = level;
     int maxB = 0;
-    for (int i = 0; i < n; ++i) {
-        const Instance &I = *m[i].I;
-        Bf16BatchMember &d = a.mem[i];
-        d.J = I.Jbf;
-        d.Ma = m[i].Ma;
-        d.Mb = m[i].Mb;
-        d.table = m[i].table;
-        d.hhalf = I.has_h ? I.hhalf : nullptr;
-        d.ldk = I.Np;
-        d.R = m[i].R;
-        d.nrt = (m[i].R + 127) / 128;
-        d.kpad = (I.N + HBK - 1) / HBK * HBK;
-        d.ldt = m[i].ldt;
-        d.kmax = m[i].kmax;
-        d.lslot = m[i].lslot;
-        d.gamma = m[i].gamma;
+    for (int i = 0; i < n; ++i)
         maxB = std::max(maxB, m[i].B);
-    }
+    // tile shape of a phase launch: 128 x 128 (128-deep slabs) when the
+    // members' tiles of that shape fill the chip, else 64 x 64 (four waves,
+    // several workgroups per CU); both reduce every element in the same order,
+    // so results do not depend on the choice.  MARS_BATCH_TILE=0|3 forces one.
+    const char *fv = std::getenv("MARS_BATCH_TILE");
+    const int forced = (fv && (fv[0] == '0' || fv[0] == '3') && !fv[1]) ? fv[0] - '0' : -1;
     for (int ph = 0; ph < maxB; ++ph) {
+        int t128 = 0;
+        for (int i = 0; i < n; ++i)
+            if (ph < m[i].B && m[i].pb[ph + 1] > m[i].pb[ph])
+                t128 += ((m[i].R + 127) / 128) * ((m[i].pb[ph + 1] - m[i].pb[ph] + 127) / 128);
+        const bool small = forced >= 0 ? forced == 3 : t128 < 256;
+        const int bm = small ? 64 : 128, bn = small ? 64 : 128, bk = small ? 64 : HBK;
+        for (int i = 0; i < n; ++i) {
+            const Instance &I = *m[i].I;
+            Bf16BatchMember &d = a.mem[i];
+            d.J = I.Jbf;
+            d.Ma = m[i].Ma;
+            d.Mb = m[i].Mb;
+            d.table = m[i].table;
+            d.hhalf = I.has_h ? I.hhalf : nullptr;
+            d.ldk = I.Np;
+            d.R = m[i].R;
+            d.nrt = (m[i].R + bm - 1) / bm;
+            d.kpad = (I.N + bk - 1) / bk * bk;
+            d.ldt = m[i].ldt;
+            d.kmax = m[i].kmax;
+            d.lslot = m[i].lslot;
+            d.gamma = m[i].gamma;
+        }
         int ns = 0, tile0 = 0;
         for (int i = 0; i < n; ++i) {
             if (ph >= m[i].B || m[i].pb[ph + 1] <= m[i].pb[ph])
@@ -229,7 +242,7 @@ hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipSt
             sl.member = i;
             sl.p0 = m[i].pb[ph];
             sl.p1 = m[i].pb[ph + 1];
-            sl.nct = (sl.p1 - sl.p0 + 127) / 128;
+            sl.nct = (sl.p1 - sl.p0 + bn - 1) / bn;
             sl.tile0 = tile0;
             sl.blend = (sl.p0 % 8) != 0;
             tile0 += (a.mem[i].nrt * sl.nct + 7) / 8 * 8;  // next member starts on a multiple of 8
@@ -237,7 +250,11 @@ hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipSt
         a.nslot = ns;
         if (ns == 0)
             continue;
-        hipLaunchKernelGGL((k_dense_phase_bf16_batch<128, 128, 4, 4, 2, HBK>), dim3(tile0), dim3(1024), 0, s, a);
+        if (small)
+            hipLaunchKernelGGL((k_dense_phase_bf16_batch<64, 64, 2, 2, 2, 64>), dim3(tile0), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_dense_phase_bf16_batch<128, 128, 4, 4, 2, HBK>), dim3(tile0), dim3(1024), 0, s,
+                               a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;

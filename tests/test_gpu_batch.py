@@ -45,10 +45,15 @@ def _pinned(M):
 
 
 @pytest.mark.parametrize("graph", ["1", "0"])
-def test_batch_equals_alone(graph, monkeypatch):
+@pytest.mark.parametrize("tile", ["", "0", "3"])
+def test_batch_equals_alone(graph, tile, monkeypatch):
     """Steps run as one captured graph per membership (replayed while the
     membership holds) or sweep by sweep; both equal the solves alone."""
     monkeypatch.setenv("MARS_BATCH_GRAPH", graph)
+    if tile:
+        monkeypatch.setenv("MARS_BATCH_TILE", tile)  # phase tiles 128 x 128 (0) or 64 x 64 (3) forced
+    else:
+        monkeypatch.delenv("MARS_BATCH_TILE", raising=False)
     M = _mars()
     import torch
 
