@@ -4,7 +4,10 @@ Requests (an instance, a number of runs, a schedule, a seed and an arrival
 time) are admitted as soon as they have arrived and both an active slot and
 enough HBM are free; each admitted request keeps its couplings and run state
 resident on the GPU while its solve runs on one of a pool of streams, so the
-work of different requests overlaps on the device.  Completed requests free
+work of different requests overlaps on the device.  An admitted request's
+dense instance is created on a worker thread (host validation of the
+couplings, encodings and upload: about 0.1 s for N = 10^4), and its solve is
+enqueued once it is ready, so that creation overlaps the GPU's work.  Completed requests free
 their slot at once and their memory when the GPU is idle or as soon as an
 arrived request waits for memory (releasing device memory synchronises the
 device, so it is not done while it would only stall running solves).
@@ -223,7 +226,7 @@ class MarsServer:
     """Runs a stream of requests with continuous batching on the current GPU."""
 
     def __init__(self, hbm_budget: int | None = None, max_active: int = 8, n_streams: int = 4, batching: bool = True,
-                 batch_sweeps: int = 8, grouping: bool = True):
+                 batch_sweeps: int = 8, grouping: bool = True, create_workers: int = 4):
         import torch
 
         from . import mars as M
@@ -241,6 +244,11 @@ class MarsServer:
         self.batch_sweeps = int(batch_sweeps)
         self.batch_stream = torch.cuda.Stream() if batching else None
         self.grouping = grouping
+        from concurrent.futures import ThreadPoolExecutor
+
+        # instance creation off the serving loop (the library releases the
+        # interpreter lock in its calls)
+        self.creator = ThreadPoolExecutor(max_workers=max(1, int(create_workers)))
 
     def run(self, requests, time_scale: float = 1.0, verbose: bool = False, progress=None,
             progress_every_s: float = 30.0):
@@ -262,6 +270,7 @@ class MarsServer:
         stream_load = [0] * len(self.streams)
         peak_running = peak_batch = 0
         n_grouped = 0  # requests enqueued in groups of two or more
+        reserved = {"batch": 0, "solo": 0}  # admitted, instance still being created
         t0 = time.perf_counter()
         last_report = t0
         try:
@@ -301,24 +310,53 @@ class MarsServer:
                     graveyard = []
                     progressed = True
                 # admit: batch members up to the batch's capacity, other
-                # requests up to max_active on the stream pool
-                room = {"batch": cap - len(batch) if batch is not None else 0,
-                        "solo": self.max_active - sum(stream_load)}
+                # requests up to max_active on the stream pool (counting the
+                # admitted requests whose instance is still being created)
+                room = {"batch": cap - len(batch) - reserved["batch"] if batch is not None else 0,
+                        "solo": self.max_active - sum(stream_load) - reserved["solo"]}
+
+                decided = {}
 
                 def accept(req):
                     cls = "batch" if room["batch"] > 0 and batchable(req) else "solo"
                     if room[cls] <= 0:
                         return False
                     room[cls] -= 1
+                    decided[req.rid] = cls
                     return True
 
-                grouped = []  # sparse requests admitted in this pass: enqueued together
                 for req, fp in sched.admissible(now, accept):
-                    inst = M.Instance.from_inputs(req.materialize())
-                    buf = torch.empty(256, dtype=torch.uint8, pin_memory=True)
-                    job = {"req": req, "inst": inst, "event": None, "buf": buf, "fp": fp,
+                    cls = decided[req.rid]
+                    reserved[cls] += 1
+                    # a dense instance (host validation of N^2 couplings,
+                    # encodings, upload) is created on a worker thread while
+                    # the GPU runs the others; a sparse one (about a
+                    # millisecond) here, so that the sparse requests admitted
+                    # together are ready together and share launches
+                    if req.dense:
+                        creating = self.creator.submit(M.Instance.from_inputs, req.materialize())
+                    else:
+                        from concurrent.futures import Future
+
+                        creating = Future()
+                        creating.set_result(M.Instance.from_inputs(req.materialize()))
+                    job = {"req": req, "inst": None, "event": None, "fp": fp, "cls": cls, "creating": creating,
+                           "buf": torch.empty(256, dtype=torch.uint8, pin_memory=True),
                            "admitted": (time.perf_counter() - t0) / time_scale}
-                    if batch is not None and len(batch) < cap and batchable(req):
+                    running.append(job)
+                    if verbose:
+                        print("admit", req.rid, "N", req.N, "runs", req.runs, cls, flush=True)
+                    progressed = True
+                # enqueue the admitted requests whose instance is ready
+                grouped = []  # sparse requests ready in this pass: enqueued together
+                for job in running:
+                    if job["inst"] is not None or not job["creating"].done():
+                        continue
+                    job["inst"] = job.pop("creating").result()
+                    req, inst, buf = job["req"], job["inst"], job["buf"]
+                    reserved[job["cls"]] -= 1
+                    progressed = True
+                    if job["cls"] == "batch":
                         with torch.cuda.stream(self.batch_stream):
                             job["outs"] = batch.add(inst, req.runs, req.schedule, req.seed, req.rid, buf)
                         job["stream"] = -1
@@ -334,11 +372,7 @@ class MarsServer:
                         job["event"] = ev
                         job["stream"] = k
                         stream_load[k] += 1
-                    running.append(job)
-                    if verbose:
-                        print("admit", req.rid, "N", req.N, "runs", req.runs, "stream", job.get("stream"), flush=True)
-                    progressed = True
-                # sparse requests admitted together share the solver's launches
+                # sparse requests ready together share the solver's launches
                 # (mars_solve_group_async): one stream, one completion event
                 for g0 in range(0, len(grouped), GROUP_MAX):
                     part = grouped[g0:g0 + GROUP_MAX]

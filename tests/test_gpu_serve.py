@@ -15,7 +15,9 @@ def test_served_results_equal_alone(batching, grouping):
     from paper_1907_05124_amd import mars as M
     from paper_1907_05124_amd import serve as S
 
-    reqs = S.mixed_stream(16, rate=500.0, seed=5, n_lo=100, n_hi=1500, runs_lo=256, runs_hi=1024, levels=60)
+    # a burst (every request arrives at t = 0): the first admission pass takes
+    # several sparse requests at once, which grouping then enqueues together
+    reqs = S.mixed_stream(16, rate=1e9, seed=5, n_lo=100, n_hi=1500, runs_lo=256, runs_hi=1024, levels=60)
     for r in reqs:
         r.instance = r.materialize()
     announce("serve mixed", len(reqs), "batching", batching, "grouping", grouping)
