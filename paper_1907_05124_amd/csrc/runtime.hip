@@ -362,19 +362,28 @@ static mars_status create_dense(const float *J, const float *h, int N, Instance 
     MARS_HIP(hipMemsetAsync(I->J, 0, sizeof(float) * Np * Np, I->own_stream));
     MARS_HIP(hipMemcpy2DAsync(I->J, sizeof(float) * Np, J, sizeof(float) * N, sizeof(float) * N, N,
                               hipMemcpyHostToDevice, I->own_stream));
-    if ((st = dev_alloc(&I->Jfix, (size_t)N * N)) != MARS_OK)
-        return st;
+    // the fixed-point copy is a temporary of the limb encoding: stream-ordered
+    // allocation and release, so that creating an instance does not wait for
+    // the device's other work (a plain free synchronises the device)
+    {
+        void *p = nullptr;
+        hipError_t e = hipMallocAsync(&p, sizeof(*I->Jfix) * (size_t)N * N, I->own_stream);
+        if (e != hipSuccess)
+            return e == hipErrorOutOfMemory ? set_error(MARS_E_OOM, "device memory exhausted")
+                                            : hip_error(e, "hipMallocAsync");
+        I->Jfix = static_cast<decltype(I->Jfix)>(p);
+    }
     launch_dense_fixpoint(*I, I->own_stream);
     MARS_HIP(hipGetLastError());
     if ((st = dev_alloc(&I->Jlimb, (size_t)I->nlimb * I->Me * I->Ke)) != MARS_OK)
         return st;
     launch_dense_limbs(*I, I->own_stream);
     MARS_HIP(hipGetLastError());
+    MARS_HIP(hipFreeAsync(I->Jfix, I->own_stream));
+    I->Jfix = nullptr;
     if ((st = upload_h(I, h, I->Np)) != MARS_OK)
         return st;
     MARS_HIP(hipStreamSynchronize(I->own_stream));
-    MARS_HIP(hipFree(I->Jfix));
-    I->Jfix = nullptr;
     return MARS_OK;
 }
 
@@ -1548,78 +1557,91 @@ mars_status mars_solve_group_async(int32_t count, mars_instance *const *insts, c
     }
     MARS_HIP(hipSetDevice(L[0]->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::vector<GraphSolve> G(count);
-    std::vector<SparsePlan> P(count);
-    mars_status st;
-    for (int i = 0; i < count; ++i) {
-        Instance *I = L[i];
-        Workspace &w = I->ws;
-        const int R = runs[i];
-        if ((st = order_begin(I, s)) != MARS_OK)
-            return st;
-        if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK ||
-            (st = ensure(w.spins, (size_t)R * I->N)) != MARS_OK)
-            return st;
-        double *E = energies ? energies[i] : nullptr;
-        if (!E) {
-            if ((st = ensure(w.energies, sizeof(double) * R)) != MARS_OK)
+    // members whose stream work has begun: on an error their instances still
+    // record the end of what was enqueued, so later solves wait for it
+    int begun = 0;
+    auto enqueue = [&]() -> mars_status {
+        std::vector<GraphSolve> G(count);
+        std::vector<SparsePlan> P(count);
+        mars_status st;
+        for (int i = 0; i < count; ++i) {
+            Instance *I = L[i];
+            Workspace &w = I->ws;
+            const int R = runs[i];
+            if ((st = order_begin(I, s)) != MARS_OK)
                 return st;
-            E = (double *)w.energies.p;
-        }
-        launch_stamp(result_stamp((mars_result *)w.result.p), s);
-        if ((st = graph_pre(I, R, scheds[i], seeds[i], nullptr, nullptr, nullptr, (int8_t *)w.spins.p, E, nullptr,
-                            0, &G[i], s)) != MARS_OK)
-            return st;
-        // a sparse solve on the LDS-resident solver is planned; any other is
-        // enqueued here
-        if ((st = plan_graph_solve(*I, G[i], s, &P[i])) != MARS_OK)
-            return st;
-    }
-    // one launch per kernel among the planned solves
-    std::vector<bool> launched(count, false);
-    for (int i = 0; i < count; ++i) {
-        if (!P[i].fn || launched[i])
-            continue;
-        std::vector<SparsePlan> same{P[i]};
-        launched[i] = true;
-        for (int j = i + 1; j < count && P[i].gfn; ++j)
-            if (!launched[j] && P[j].fn && P[j].gfn == P[i].gfn) {
-                same.push_back(P[j]);
-                launched[j] = true;
+            begun = i + 1;
+            if ((st = ensure(w.result, sizeof(mars_result) + 64)) != MARS_OK ||
+                (st = ensure(w.spins, (size_t)R * I->N)) != MARS_OK)
+                return st;
+            double *E = energies ? energies[i] : nullptr;
+            if (!E) {
+                if ((st = ensure(w.energies, sizeof(double) * R)) != MARS_OK)
+                    return st;
+                E = (double *)w.energies.p;
             }
-        GraphGroup *hd = nullptr, *dd = nullptr;
-        Instance *lead = L[i];
-        if (same.size() > 1) {
-            // the leader's descriptor: its previous copy must have run before
-            // the host copy is rewritten
-            if (lead->grp_pending)
-                MARS_HIP(hipEventSynchronize(lead->grp_event));
-            if (!lead->grp_event)
-                MARS_HIP(hipEventCreateWithFlags(&lead->grp_event, hipEventDisableTiming));
-            lead->grp_host.resize(sizeof(GraphGroup));
-            if ((st = ensure(lead->ws.grp, sizeof(GraphGroup))) != MARS_OK)
+            launch_stamp(result_stamp((mars_result *)w.result.p), s);
+            if ((st = graph_pre(I, R, scheds[i], seeds[i], nullptr, nullptr, nullptr, (int8_t *)w.spins.p, E, nullptr,
+                                0, &G[i], s)) != MARS_OK)
                 return st;
-            hd = reinterpret_cast<GraphGroup *>(lead->grp_host.data());
-            dd = reinterpret_cast<GraphGroup *>(lead->ws.grp.p);
+            // a sparse solve on the LDS-resident solver is planned; any other is
+            // enqueued here
+            if ((st = plan_graph_solve(*I, G[i], s, &P[i])) != MARS_OK)
+                return st;
         }
-        hipError_t e = launch_sparse_plans(same.data(), (int)same.size(), hd, dd, s);
-        if (e != hipSuccess)
-            return hip_error(e, "shared sparse solve launch");
-        if (hd) {
-            MARS_HIP(hipEventRecord(lead->grp_event, s));
-            lead->grp_pending = true;
+        // one launch per kernel among the planned solves
+        std::vector<bool> launched(count, false);
+        for (int i = 0; i < count; ++i) {
+            if (!P[i].fn || launched[i])
+                continue;
+            std::vector<SparsePlan> same{P[i]};
+            launched[i] = true;
+            for (int j = i + 1; j < count && P[i].gfn; ++j)
+                if (!launched[j] && P[j].fn && P[j].gfn == P[i].gfn) {
+                    same.push_back(P[j]);
+                    launched[j] = true;
+                }
+            GraphGroup *hd = nullptr, *dd = nullptr;
+            Instance *lead = L[i];
+            if (same.size() > 1) {
+                // the leader's descriptor: its previous copy must have run before
+                // the host copy is rewritten
+                if (lead->grp_pending)
+                    MARS_HIP(hipEventSynchronize(lead->grp_event));
+                if (!lead->grp_event)
+                    MARS_HIP(hipEventCreateWithFlags(&lead->grp_event, hipEventDisableTiming));
+                lead->grp_host.resize(sizeof(GraphGroup));
+                if ((st = ensure(lead->ws.grp, sizeof(GraphGroup))) != MARS_OK)
+                    return st;
+                hd = reinterpret_cast<GraphGroup *>(lead->grp_host.data());
+                dd = reinterpret_cast<GraphGroup *>(lead->ws.grp.p);
+            }
+            hipError_t e = launch_sparse_plans(same.data(), (int)same.size(), hd, dd, s);
+            if (e != hipSuccess)
+                return hip_error(e, "shared sparse solve launch");
+            if (hd) {
+                MARS_HIP(hipEventRecord(lead->grp_event, s));
+                lead->grp_pending = true;
+            }
         }
-    }
-    for (int i = 0; i < count; ++i) {
-        Instance *I = L[i];
-        mars_result *res_dev = (mars_result *)I->ws.result.p;
-        if ((st = graph_post(I, G[i], best_spins ? best_spins[i] : nullptr, res_dev, result_best(res_dev), s)) !=
-            MARS_OK)
-            return st;
-        if (res_pinned)
-            MARS_HIP(hipMemcpyAsync(&res_pinned[i], res_dev, sizeof(mars_result), hipMemcpyDeviceToHost, s));
-        if ((st = order_end(I, s)) != MARS_OK)
-            return st;
+        for (int i = 0; i < count; ++i) {
+            Instance *I = L[i];
+            mars_result *res_dev = (mars_result *)I->ws.result.p;
+            if ((st = graph_post(I, G[i], best_spins ? best_spins[i] : nullptr, res_dev, result_best(res_dev), s)) !=
+                MARS_OK)
+                return st;
+            if (res_pinned)
+                MARS_HIP(hipMemcpyAsync(&res_pinned[i], res_dev, sizeof(mars_result), hipMemcpyDeviceToHost, s));
+            if ((st = order_end(I, s)) != MARS_OK)
+                return st;
+        }
+        return MARS_OK;
+    };
+    const mars_status st = enqueue();
+    if (st != MARS_OK) {
+        for (int i = 0; i < begun; ++i)
+            (void)order_end(L[i], s);
+        return st;
     }
     return MARS_OK;
 }
