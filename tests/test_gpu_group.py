@@ -119,3 +119,40 @@ def test_group_rejects():
     finally:
         a.close()
         d.close()
+
+
+def test_group_with_unshared_paths():
+    """Members that cannot share a launch sit beside ones that do: a solve
+    with no temperature level (start-only path), a sparse instance beyond LDS
+    (device-memory solver) and a lattice beyond LDS; every member equals its
+    solve alone."""
+    M = _mars()
+    torch = require_gpu()
+    big = I.er_instance(48000, 3, p=4.0 / 47999, weights="pm1")
+    lat = I.lattice_instance((28, 28, 28), 5)
+    small = [I.er_instance(300, 1, p=0.02, weights="pm1"), I.er_instance(500, 2, avg_degree=5.0, weights="pm1"),
+             I.er_instance(400, 6, p=0.015, weights="pm1")]
+    members = [("small a", small[0], 1031, _rel_sched(small[0], precision="fp32"), 1),
+               ("no level", small[1], 1100, _rel_sched(small[1], precision="fp32", steps=0), 2),
+               ("beyond LDS", big, 64, _rel_sched(big, precision="fp32", steps=30), 3),
+               ("lattice beyond LDS", lat, 32, _rel_sched(lat, precision="fp64", steps=20), 4),
+               ("small b", small[2], 2048, _rel_sched(small[2], precision="fp32"), 5)]
+    insts = [M.Instance.from_inputs(m[1]) for m in members]
+    try:
+        alone = []
+        for (label, _, R, sch, seed), g in zip(members, insts):
+            announce("group unshared: alone", label, R)
+            alone.append(g.solve_ex(R, sch, seed, want_best=True, want_energies=True))
+        stream = torch.cuda.Stream()
+        buf = torch.zeros(len(members) * C.sizeof(M.Result), dtype=torch.uint8, pin_memory=True)
+        announce("group unshared: together", len(members))
+        outs = M.Instance.solve_group_async([(g, m[2], m[3], m[4]) for g, m in zip(insts, members)], buf,
+                                            stream=stream, want_energies=True)
+        stream.synchronize()
+        for i, ((label, _, R, _, _), a) in enumerate(zip(members, alone)):
+            assert solve_summary(M.Instance.read_result(buf, i)) == solve_summary(a["result"]), label
+            assert np.array_equal(outs[i]["energies"].cpu().numpy(), a["energies"].cpu().numpy()), label
+            assert np.array_equal(outs[i]["best_spins"].cpu().numpy(), a["best_spins"].cpu().numpy()), label
+    finally:
+        for g in insts:
+            g.close()
