@@ -168,6 +168,10 @@ static mars_status graph_solve_or_plan(const Instance &I, const GraphSolve &g, h
             stop = a.rs.first + a.rs.count;
         a.ttab = std::max(0, stop - a.rs.first);
     }
+    // one sweep per level on a geometric schedule: every live run anneals
+    // exactly one sweep per level of the same level range, so a block's sweep
+    // count is known and its per-sweep vote can be left out
+    a.fixed_sweeps = (a.rs.kind == MARS_GEOMETRIC && !trackd) ? a.ttab : 0;
     a.max_sweeps = sc.max_sweeps;
     a.d_min = sc.d_min;
     a.damping = sc.damping;

@@ -125,6 +125,7 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
     if (threadIdx.x == 0)
         vote[0] = vote[1] = 0u;
     __syncthreads();
+    unsigned v_first = 0u;
     for (unsigned nvote = 0;; ++nvote) {
         // the runs' level state, advanced at the end of the previous sweep
         C scale[VEC];
@@ -138,7 +139,16 @@ __global__ __launch_bounds__(1024) void k_lattice_solve(GraphArgs a, int lg_rpw)
         }
         // block-uniform: leave when no run of the block anneals; the fast
         // update only while every run of the block does
-        const unsigned v = block_vote(vote, nvote, code);
+        // (with a known sweep count only the first sweep votes: it decides
+        // whether the block has a run at all and whether every run anneals,
+        // which holds until the last sweep)
+        unsigned v;
+        if (a.fixed_sweeps > 0 && nvote > 0) {
+            v = nvote < (unsigned)a.fixed_sweeps ? v_first : 0u;
+        } else {
+            v = block_vote(vote, nvote, code);
+            v_first = v;
+        }
         if (!(v & 1u))
             break;
         const bool all = !(v & 2u);

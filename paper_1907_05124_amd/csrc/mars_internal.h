@@ -341,6 +341,7 @@ struct GraphArgs {
     const int32_t *cls;
     int long_rows;  // sparse: average degree >= 16, entry groups are read ahead
     int ttab;       // geometric schedules: levels in the block's LDS level table (0: none)
+    int fixed_sweeps;  // > 0: every live run anneals exactly this many sweeps (geometric, one per level)
     // lattice
     int dim, L0, L1, L2;
     const uint8_t *bondbits;

@@ -172,6 +172,7 @@ __device__ __forceinline__ void sparse_solve_block(const GraphArgs &a, int lg_rp
     if (threadIdx.x == 0)
         vote[0] = vote[1] = 0u;
     __syncthreads();
+    unsigned v_first = 0u;
     for (unsigned nvote = 0;; ++nvote) {
         // the level state of the lane's runs (part + LPS k of its group),
         // advanced at the end of the previous sweep
@@ -187,7 +188,16 @@ __device__ __forceinline__ void sparse_solve_block(const GraphArgs &a, int lg_rp
         }
         // block-uniform: leave when no run of the block anneals; the fast
         // update only while every run of the block does
-        const unsigned v = block_vote(vote, nvote, code);
+        // (with a known sweep count only the first sweep votes: it decides
+        // whether the block has a run at all and whether every run anneals,
+        // which holds until the last sweep)
+        unsigned v;
+        if (a.fixed_sweeps > 0 && nvote > 0) {
+            v = nvote < (unsigned)a.fixed_sweeps ? v_first : 0u;
+        } else {
+            v = block_vote(vote, nvote, code);
+            v_first = v;
+        }
         if (!(v & 1u))
             break;
         const bool all = !(v & 2u);
