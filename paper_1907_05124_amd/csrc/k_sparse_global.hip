@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kGlobalThreads) void k_sparse_global(SparseGlobalAr
                     const C ov = LStore<S>::ld(old.v[e]);
                     C n = damp ? ((C)1 - gam) * ov + gam * th : th;
                     n = done[e] ? ov : n;  // a finished run keeps its state
-                    nw.v[e] = done[e] ? old.v[e] : lds_keep_sign<S>(n);
+                    nw.v[e] = done[e] ? old.v[e] : (damp ? lds_keep_sign<S>(n) : LStore<S>::st(n));
                     if (trackd && !done[e]) {
                         // the sweep's largest change reaches d_min iff one of
                         // its changes does (the comparison in the precision

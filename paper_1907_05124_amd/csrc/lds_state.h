@@ -239,8 +239,14 @@ static_assert(RUN_AREA_BYTES <= RUN_AREA_MAX, "per-run LDS area exceeds the laun
 // and keeps the short form.
 //
 // ACC = 1 (fp16 storage of the sparse solver): only tanh(a) = a below
-// |a| = 2^-12 (a^2/3 < 2^-25 relative), so that a decayed value stays
-// nonzero with its sign (see lds_keep_sign) instead of becoming exactly 0.
+// |a| = 2^-12 (a^2/3 < 2^-25 relative), its magnitude floored at 2^-24 (the
+// smallest fp16 subnormal) with the sign of a, so that a decayed value stays
+// nonzero with its sign instead of becoming exactly 0: every value this
+// returns converts to a nonzero fp16 (a zero field gives +2^-24, the state of
+// an isolated spin; its rounded spin is +1 as for 0).  Values between 2^-25
+// and 2^-24 round to 2^-24 anyway, so the floor only changes what would
+// round to 0; a damped update, which can cancel to a smaller value, stores
+// through lds_keep_sign.
 template <int ACC = 0>
 __device__ inline float l_tanh_run(float phi, float ts)
 {
@@ -257,7 +263,8 @@ __device__ inline float l_tanh_run(float phi, float ts)
         return fabsf(a) < 0.625f ? a * q : t;
     } else if constexpr (ACC == 1) {
         const float a = x * -0.34657359027997264f;
-        return fabsf(a) < 0x1p-12f ? a : t;
+        const float f = __builtin_copysignf(__builtin_fmaxf(fabsf(a), 0x1p-24f), a);
+        return fabsf(a) < 0x1p-12f ? f : t;
     }
     return t;
 }
@@ -265,8 +272,9 @@ __device__ inline float l_tanh_run(float phi, float ts)
 // Store of a magnetisation that keeps its sign through fp16 underflow: a
 // nonzero value below half the smallest fp16 subnormal (2^-24) would round to
 // 0, losing the direction a decayed run grows back in once T falls below its
-// instability; it is stored as +-2^-24 instead.  Other storage types store
-// plainly.
+// instability; it is stored as +-2^-24 instead (needed after a damped
+// update: an undamped one stores the fp16-storage tanh above, whose
+// magnitude is never below 2^-24).  Other storage types store plainly.
 template <typename S>
 __device__ inline S lds_keep_sign(typename LStore<S>::C v)
 {

@@ -316,7 +316,7 @@ __device__ __forceinline__ void sparse_solve_block(const GraphArgs &a, int lg_rp
                             // convergence tracking: the old value is not needed
 #pragma unroll
                             for (int e = 0; e < VEC; ++e)
-                                nw.v[e] = lds_keep_sign<S>(l_tanh_run<TA>(own[e], scale[e]));
+                                nw.v[e] = LStore<S>::st(l_tanh_run<TA>(own[e], scale[e]));
                             lds_put<S, VEC>(reinterpret_cast<S *>(wb + o_slot), nw);
                             continue;
                         }
@@ -327,7 +327,7 @@ __device__ __forceinline__ void sparse_solve_block(const GraphArgs &a, int lg_rp
                             const C o = LStore<S>::ld(old.v[e]);
                             C n = DAMP ? ((C)1 - g) * o + g * th : th;
                             n = done[e] ? o : n;  // a finished run keeps its state
-                            nw.v[e] = done[e] ? old.v[e] : lds_keep_sign<S>(n);
+                            nw.v[e] = done[e] ? old.v[e] : (DAMP ? lds_keep_sign<S>(n) : LStore<S>::st(n));
                             const C dd = n > o ? n - o : o - n;
                             dloc[e] = dd > dloc[e] ? dd : dloc[e];
                         }
@@ -339,13 +339,13 @@ __device__ __forceinline__ void sparse_solve_block(const GraphArgs &a, int lg_rp
                             const uint32_t o_e = o_slot + (uint32_t)((part + LPS * k) * sizeof(S));
                             const C th = l_tanh_run<TA>(own[k], scale[k]);
                             if constexpr (FAST) {
-                                *reinterpret_cast<S *>(wb + o_e) = lds_keep_sign<S>(th);
+                                *reinterpret_cast<S *>(wb + o_e) = LStore<S>::st(th);
                             } else {
                                 const S os = *reinterpret_cast<const S *>(mb + o_e);
                                 const C o = LStore<S>::ld(os);
                                 C n = DAMP ? ((C)1 - g) * o + g * th : th;
                                 n = done[k] ? o : n;
-                                *reinterpret_cast<S *>(wb + o_e) = done[k] ? os : lds_keep_sign<S>(n);
+                                *reinterpret_cast<S *>(wb + o_e) = done[k] ? os : (DAMP ? lds_keep_sign<S>(n) : LStore<S>::st(n));
                                 const C dd = n > o ? n - o : o - n;
                                 dloc[k] = dd > dloc[k] ? dd : dloc[k];
                             }
