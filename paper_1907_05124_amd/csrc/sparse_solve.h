@@ -9,11 +9,17 @@
 //    variant writes a second copy and swaps after each sweep.
 //  * VEC consecutive runs share each entry read (neighbour slot and weight),
 //    and the VEC values of a neighbour arrive in one LDS read.
-//  * LPS adjacent lanes share one (slot, run group): lane p of the group sums
-//    the entry groups p, p + LPS, ...; the partial fields are combined by a
-//    reduce-scatter over the group's lanes (DPP moves inside a quad), after
-//    which lane p holds the whole field of runs p, p + LPS, ... and updates
-//    those.  Long rows on narrow colour classes (few slots per phase, tens of
+//  * LPS lanes share one (slot, run group): lane p of the group sums the
+//    entry groups p, p + LPS, ...; the partial fields are combined by a
+//    reduce-scatter over the group's lanes (DPP moves), after which lane p
+//    holds the whole field of runs p, p + LPS, ... and updates those.  With
+//    two lanes per slot and at least eight run groups, the two parts of a
+//    slot sit eight lanes apart (exchange by a rotation of the 16-lane row):
+//    each eight consecutive lanes then read eight consecutive 16-byte pieces
+//    of one neighbour's row, which covers every LDS bank once, where
+//    interleaved parts read two rows at the same bank offsets (a two-way
+//    conflict on every neighbour read).  Otherwise the lanes of a group are
+//    adjacent within a quad.  Long rows on narrow colour classes (few slots per phase, tens of
 //    terms per slot) otherwise leave most lanes idle, each of the busy ones
 //    summing a long serial chain; the split shortens the chain and the update
 //    (tanh) is still evaluated once per spin-update.
@@ -45,21 +51,24 @@ __device__ inline C entry_weight(uint32_t cb)
         return (C)((int32_t)cb >> 24);
 }
 
-// value of the lane whose index differs in bit 0 (QX = 1) or bit 1 (QX = 2),
-// within the lane's quad (DPP quad permutation; every lane of the quad active)
-template <int QX>
-__device__ __forceinline__ float quad_xor(float v)
+// value of the lane whose index differs in bit 0 (X = 1) or bit 1 (X = 2),
+// within the lane's quad (DPP quad permutation), or in bit 3 (X = 8: a
+// rotation of the lane's 16-lane row by eight); both lanes active
+template <int X>
+__device__ __forceinline__ float lane_xor(float v)
 {
-    constexpr int ctrl = QX == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+    static_assert(X == 1 || X == 2 || X == 8, "DPP exchange distance");
+    constexpr int ctrl = X == 1 ? 0xB1 : X == 2 ? 0x4E : 0x128;  // quad_perm [1,0,3,2] / [2,3,0,1] / row_ror:8
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, false));
 }
 
 // Reduce-scatter of the VEC partial fields over the LPS lanes of a group:
 // afterwards own[k] is the field of run part + LPS * k summed over the group's
 // lanes.  Each sum is formed by one lane in a fixed order ((p0 + p1) + (p2 +
-// p3) for four lanes), so the result does not depend on scheduling.
+// p3) for four lanes), so the result does not depend on scheduling.  far:
+// the two lanes of a pair are eight apart instead of adjacent (LPS = 2).
 template <int VEC, int LPS>
-__device__ __forceinline__ void split_reduce(const float (&phi)[VEC], float (&own)[VEC / LPS], int part)
+__device__ __forceinline__ void split_reduce(const float (&phi)[VEC], float (&own)[VEC / LPS], int part, bool far)
 {
     if constexpr (LPS == 1) {
 #pragma unroll
@@ -73,7 +82,7 @@ __device__ __forceinline__ void split_reduce(const float (&phi)[VEC], float (&ow
         for (int j = 0; j < VEC / 2; ++j) {
             const float keep = b ? phi[2 * j + 1] : phi[2 * j];
             const float send = b ? phi[2 * j] : phi[2 * j + 1];
-            half[j] = keep + quad_xor<1>(send);  // run 2j + b
+            half[j] = keep + (far ? lane_xor<8>(send) : lane_xor<1>(send));  // run 2j + b
         }
         if constexpr (LPS == 2) {
 #pragma unroll
@@ -85,7 +94,7 @@ __device__ __forceinline__ void split_reduce(const float (&phi)[VEC], float (&ow
             const bool c = (part & 2) != 0;
             const float keep = c ? half[1] : half[0];
             const float send = c ? half[0] : half[1];
-            own[0] = keep + quad_xor<2>(send);
+            own[0] = keep + lane_xor<2>(send);
         }
     }
 }
@@ -115,10 +124,15 @@ __device__ __forceinline__ void sparse_solve_block(const GraphArgs &a, int lg_rp
     const int tq_io = threadIdx.x / nq;
     const int Tq_io = blockDim.x / nq;
     const int run0_io = bid * rpw + q0_io;
-    // sweeps: LPS adjacent lanes per (slot, run group)
-    const int part = LPS > 1 ? (int)(threadIdx.x % LPS) : 0;
-    const int q0 = ((threadIdx.x / LPS) % nq) * VEC;
-    const int tq = threadIdx.x / (LPS * nq);
+    // sweeps: LPS lanes per (slot, run group), LPS * nq consecutive lanes
+    // per slot; two lanes per slot with at least eight run groups: lane bits
+    // [run group mod 8 | part | run group / 8 | slot], else [part | run group
+    // | slot]
+    const int tid = (int)threadIdx.x;
+    const bool far = LPS == 2 && nq >= 8;
+    const int part = LPS == 1 ? 0 : far ? (tid >> 3) & 1 : tid % LPS;
+    const int q0 = (far ? (tid & 7) | (((tid >> 4) & (nq / 8 - 1)) << 3) : (tid / LPS) % nq) * VEC;
+    const int tq = tid / (LPS * nq);
     const int Tq = blockDim.x / (LPS * nq);
 
     // initial state (Algorithm 1: s_i := rand(-1, 1)); padding slots and the
@@ -295,7 +309,7 @@ __device__ __forceinline__ void sparse_solve_block(const GraphArgs &a, int lg_rp
                         for (int e = 0; e < VEC; ++e)
                             own[e] = phi[e];
                     } else {
-                        split_reduce<VEC, LPS>(phi, own, part);
+                        split_reduce<VEC, LPS>(phi, own, part, far);
                     }
                     if (HAS_H) {
                         C hh;
