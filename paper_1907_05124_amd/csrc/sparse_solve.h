@@ -14,12 +14,11 @@
 //    reduce-scatter over the group's lanes (DPP moves), after which lane p
 //    holds the whole field of runs p, p + LPS, ... and updates those.  With
 //    two lanes per slot and at least eight run groups, the two parts of a
-//    slot sit eight lanes apart (exchange by a rotation of the 16-lane row):
-//    each eight consecutive lanes then read eight consecutive 16-byte pieces
-//    of one neighbour's row, which covers every LDS bank once, where
-//    interleaved parts read two rows at the same bank offsets (a two-way
-//    conflict on every neighbour read).  Otherwise the lanes of a group are
-//    adjacent within a quad.  Long rows on narrow colour classes (few slots per phase, tens of
+//    slot sit eight lanes apart (exchange by a rotation of the 16-lane row),
+//    so that eight consecutive lanes read eight consecutive 16-byte pieces of
+//    one neighbour's row (measured faster than adjacent pairs on long rows,
+//    though the LDS bank-conflict share did not change).  Otherwise the lanes
+//    of a group are adjacent within a quad.  Long rows on narrow colour classes (few slots per phase, tens of
 //    terms per slot) otherwise leave most lanes idle, each of the busy ones
 //    summing a long serial chain; the split shortens the chain and the update
 //    (tanh) is still evaluated once per spin-update.
