@@ -469,3 +469,38 @@ def test_lane_split_variants(case, lps, monkeypatch):
     sample = list(range(0, R, R // 32))[:32]
     check_replay(out["m"].cpu().numpy(), spl, inst, R, sch, 43, "fp32", sample,
                  label="%s lps=%s" % (case, lps))
+
+
+@pytest.mark.parametrize("case", ["er_dense_isolated", "er_int8_dense"])
+def test_lane_split_far_pairs(case, monkeypatch):
+    """Two lanes per slot with at least eight run groups per workgroup (8200
+    runs: 32 runs per workgroup, a ragged last block), where the two lanes of
+    a pair sit eight lanes apart and exchange their partial fields by a row
+    rotation: one damped fp32 level, phased and synchronous, within 1e-5 of
+    the oracle, the fp16 storage bound, and the paper's scheduler by replay
+    on 32 sampled runs (runs of one workgroup finishing levels at different
+    sweeps)."""
+    M = _mars()
+    for name in ("MARS_SPARSE_LPS", "MARS_SPARSE_VEC", "MARS_SPARSE_RPW"):
+        monkeypatch.delenv(name, raising=False)
+    inst = CASES[case]()
+    R = 8200
+    for update in ("phased", "jacobi"):
+        sch = _rel_sched(inst, precision="fp32", update=update, damping=0.5, level_count=1)
+        announce("graph far pairs damped", case, update, R)
+        with M.Instance.from_inputs(inst) as g:
+            out = g.solve_ex(R, sch, 47, want_m=True)
+        ref = O.solve(inst, R, sch, 47, run_count=R)
+        err = np.max(np.abs(out["m"].cpu().numpy().astype(np.float64) - ref["m"]))
+        assert err <= 1e-5, (update, err)
+    test_one_level_fp16_storage(case, R)
+    s = I.field_scale(inst)
+    sch = I.Schedule(kind="linear", T_lo=0.0, T_hi=2.0 * s, c_step=0.2 * s, max_sweeps=1000, d_min=1e-4,
+                     precision="fp32")
+    announce("graph far pairs paper schedule", case, R)
+    with M.Instance.from_inputs(inst) as g:
+        out = g.solve_ex(R, sch, 53, want_m=True, levels_cap=64)
+    spl = out["sweeps_per_level"].cpu().numpy()
+    assert out["result"]["sweeps_executed"] == int(spl.sum())
+    sample = list(range(0, R, R // 32))[:32]
+    check_replay(out["m"].cpu().numpy(), spl, inst, R, sch, 53, "fp32", sample, label="%s far pairs" % case)
