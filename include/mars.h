@@ -315,12 +315,16 @@ mars_status mars_auto_temperatures(mars_instance *inst, int32_t steps, uint64_t 
  *   device, or the batch already holds 16 members), MARS_E_OOM, MARS_E_DEVICE.
  * mars_batch_step: enqueues up to `sweeps` sweeps of every member; a member
  *   that reaches its last level is rounded and scored, its outputs are
- *   copied, and it leaves.  On a non-NULL stream the step's launches are
- *   captured once as a graph and replayed by later steps while no member
- *   joins or leaves and `sweeps` is unchanged (MARS_BATCH_GRAPH=0 in the
- *   environment at mars_batch_create launches sweep by sweep instead); a
- *   member that finishes inside a replayed step leaves at the step's end.
- *   Results are the same either way.  finished_tags: HOST int64 [cap]
+ *   copied, and it leaves.  On a non-NULL stream the step's per-phase
+ *   launches are captured once as a graph and replayed by later steps while
+ *   no member joins or leaves and `sweeps` is unchanged (MARS_BATCH_GRAPH=0
+ *   in the environment at mars_batch_create launches sweep by sweep
+ *   instead).  MARS_BATCH_PERSIST=1 there runs each step as one persistent
+ *   cooperative launch over every member's tiles instead (grid barriers
+ *   between update phases, the level counters advanced on the device),
+ *   while no member has more than four update phases.  A member that
+ *   finishes inside a step leaves at the step's end.  Results are the same
+ *   bit for bit on every path.  finished_tags: HOST int64 [cap]
  *   receiving the tags of the members that left during this call
  *   (*n_finished of them, never more than cap: a finished member beyond that
  *   stays, without sweeping, and leaves at a later call; sweeps = 0 only

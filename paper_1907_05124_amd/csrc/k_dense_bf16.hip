@@ -269,6 +269,106 @@ hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipSt
     return hipGetLastError();
 }
 
+template <int BM, int BN, int WM, int WN, int PF, int BK>
+static hipError_t launch_persistent_shape(Bf16BatchPersistArgs &a, int widest, hipStream_t s)
+{
+    const void *fn = reinterpret_cast<const void *>(&k_dense_batch_persistent<BM, BN, WM, WN, PF, BK>);
+    constexpr int threads = 64 * WM * WN;
+    int dev = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
+        return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0)) != hipSuccess)
+        return e;
+    // every workgroup resident at once (the grid barriers need all of them),
+    // a multiple of 8 (a tile keeps its XCD), no more than the widest phase
+    const int resident = per_cu * prop.multiProcessorCount / 8 * 8;
+    if (resident < 8)
+        return hipErrorInvalidConfiguration;
+    const int grid = std::min(resident, (widest + 7) / 8 * 8);
+    void *kargs[] = {&a};
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(threads), kargs, 0, s);
+}
+
+static_assert(sizeof(Bf16BatchPersistArgs) <= 4096, "persistent step descriptors travel as kernel arguments");
+
+hipError_t launch_batch_persistent(const BatchMemberDesc *m, int n, int *level, int sweeps, hipStream_t s)
+{
+    if (n < 1 || n > kMaxBatch || sweeps < 1)
+        return hipErrorInvalidValue;
+    int maxB = 0;
+    for (int i = 0; i < n; ++i)
+        maxB = std::max(maxB, m[i].B);
+    if (maxB > kMaxPersistPhases)
+        return hipErrorNotSupported;
+    // one tile shape for the step: 128 x 128 when every phase's tiles of that
+    // shape fill the chip, else 64 x 64 (bitwise the same results either way);
+    // MARS_BATCH_TILE=0|3 forces one
+    const char *fv = std::getenv("MARS_BATCH_TILE");
+    const int forced = (fv && (fv[0] == '0' || fv[0] == '3') && !fv[1]) ? fv[0] - '0' : -1;
+    int t128min = 1 << 30;
+    for (int ph = 0; ph < maxB; ++ph) {
+        int t128 = 0;
+        for (int i = 0; i < n; ++i)
+            if (ph < m[i].B && m[i].pb[ph + 1] > m[i].pb[ph])
+                t128 += ((m[i].R + 127) / 128) * ((m[i].pb[ph + 1] - m[i].pb[ph] + 127) / 128);
+        if (t128 > 0)
+            t128min = std::min(t128min, t128);
+    }
+    const bool small = forced >= 0 ? forced == 3 : t128min < 256;
+    const int bm = small ? 64 : 128, bn = small ? 64 : 128, bk = small ? 64 : HBK;
+    Bf16BatchPersistArgs a;
+    a.level = level;
+    a.n = n;
+    a.nph = maxB;
+    a.sweeps = sweeps;
+    for (int i = 0; i < n; ++i) {
+        const Instance &I = *m[i].I;
+        Bf16BatchMember &d = a.mem[i];
+        d.J = I.Jbf;
+        d.Ma = m[i].Ma;
+        d.Mb = m[i].Mb;
+        d.table = m[i].table;
+        d.hhalf = I.has_h ? I.hhalf : nullptr;
+        d.ldk = I.Np;
+        d.R = m[i].R;
+        d.nrt = (m[i].R + bm - 1) / bm;
+        d.kpad = (I.N + bk - 1) / bk * bk;
+        d.ldt = m[i].ldt;
+        d.kmax = m[i].kmax;
+        d.lslot = m[i].lslot;
+        d.gamma = m[i].gamma;
+        a.kmax[i] = m[i].kmax;
+        a.lslot[i] = m[i].lslot;
+    }
+    int widest = 0;
+    for (int ph = 0; ph < maxB; ++ph) {
+        int ns = 0, tile0 = 0;
+        for (int i = 0; i < n; ++i) {
+            if (ph >= m[i].B || m[i].pb[ph + 1] <= m[i].pb[ph])
+                continue;
+            Bf16BatchSlot &sl = a.slot[ph][ns++];
+            sl.member = i;
+            sl.p0 = m[i].pb[ph];
+            sl.p1 = m[i].pb[ph + 1];
+            sl.nct = (sl.p1 - sl.p0 + bn - 1) / bn;
+            sl.tile0 = tile0;
+            sl.blend = (sl.p0 % 8) != 0;
+            tile0 += (a.mem[i].nrt * sl.nct + 7) / 8 * 8;
+        }
+        a.nslot[ph] = ns;
+        a.ntile[ph] = tile0;
+        widest = std::max(widest, tile0);
+    }
+    if (widest == 0)
+        return hipSuccess;
+    return small ? launch_persistent_shape<64, 64, 2, 2, 2, 64>(a, widest, s)
+                 : launch_persistent_shape<128, 128, 4, 4, 2, HBK>(a, widest, s);
+}
+
 // s = +1 if m >= 0 else -1 into the padded operand [ldr x Ke]; optional
 // caller spins [R x N] and fp32 magnetisations [N x R]
 __global__ void k_bf16_round(const unsigned short *MT, int ldk, int N, int R, int Ke, int ldr, int8_t *spad,

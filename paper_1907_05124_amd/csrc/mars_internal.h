@@ -276,6 +276,12 @@ constexpr int kMaxBatchMembers = 16;
 // every member that has that phase, then the level advance (level[lslot] += 1
 // below kmax).  Kernel launches only, so it can be captured in a graph.
 hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipStream_t s);
+// `sweeps` sweeps of the members as one persistent cooperative launch (grid
+// barriers between phases, the level counters advanced on the device),
+// bitwise the same as that many launch_batch_sweep calls;
+// hipErrorNotSupported when a member has more phases than the launch's
+// descriptors hold.
+hipError_t launch_batch_persistent(const BatchMemberDesc *m, int n, int *level, int sweeps, hipStream_t s);
 void launch_bf16_round(const unsigned short *MT, int ldk, int N, int R, int Ke, int8_t *spad, int8_t *spins,
                        float *m_final, hipStream_t s);
 

@@ -1181,6 +1181,10 @@ struct Batch {
     bool graphs = true;
     hipGraphExec_t exec = nullptr;
     int exec_sweeps = 0;
+    // the whole step as one persistent cooperative launch (members with at
+    // most four phases; otherwise the graph or eager path).  Off by default:
+    // its grid barriers measured slower than replaying the per-phase launches
+    bool persist = false;
 };
 
 static void drop_graph(Batch &b)
@@ -1324,6 +1328,17 @@ static mars_status batch_step(Batch &b, int sweeps, int64_t *tags, int cap, int 
     BatchMemberDesc dm[kMaxBatchMembers];
     describe(b, dm);
     const int n = (int)b.members.size();
+    if (b.persist) {
+        const hipError_t e = launch_batch_persistent(dm, n, b.level, sweeps, b.s);
+        if (e == hipSuccess) {
+            for (BatchMember &m : b.members)
+                m.k = std::min(m.k + sweeps, m.d.kmax);
+            return retire(b, tags, cap, n_fin);
+        }
+        if (e != hipErrorNotSupported)
+            return hip_error(e, "persistent batch step");
+        (void)hipGetLastError();  // too many phases: the step below
+    }
     if (b.graphs && b.s) {
         // the whole step as one graph launch, captured once per membership
         if (!b.exec || b.exec_sweeps != sweeps) {
@@ -1926,6 +1941,8 @@ mars_status mars_batch_create(void *stream, mars_batch **out)
     }
     if (const char *f = std::getenv("MARS_BATCH_GRAPH"))
         b->graphs = std::atoi(f) != 0;
+    if (const char *f = std::getenv("MARS_BATCH_PERSIST"))
+        b->persist = std::atoi(f) != 0;
     *out = reinterpret_cast<mars_batch *>(b);
     return MARS_OK;
 }

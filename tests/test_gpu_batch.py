@@ -44,12 +44,24 @@ def _pinned(M):
     return torch.zeros(256, dtype=torch.uint8, pin_memory=True)
 
 
-@pytest.mark.parametrize("graph", ["1", "0"])
-@pytest.mark.parametrize("tile", ["", "0", "3"])
-def test_batch_equals_alone(graph, tile, monkeypatch):
-    """Steps run as one captured graph per membership (replayed while the
-    membership holds) or sweep by sweep; both equal the solves alone."""
+MODES = {"persistent": ("1", "1"), "graph": ("0", "1"), "eager": ("0", "0")}
+
+
+def _mode(mode, monkeypatch):
+    persist, graph = MODES[mode]
+    monkeypatch.setenv("MARS_BATCH_PERSIST", persist)
     monkeypatch.setenv("MARS_BATCH_GRAPH", graph)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("tile", ["", "0", "3"])
+def test_batch_equals_alone(mode, tile, monkeypatch):
+    """Steps run as one persistent cooperative launch (while no member has
+    more than four phases: the five-phase member below sends the steps it
+    takes part in down the graph path), as one captured graph per membership
+    (replayed while the membership holds) or sweep by sweep; every way equals
+    the solves alone."""
+    _mode(mode, monkeypatch)
     if tile:
         monkeypatch.setenv("MARS_BATCH_TILE", tile)  # phase tiles 128 x 128 (0) or 64 x 64 (3) forced
     else:
@@ -62,7 +74,7 @@ def test_batch_equals_alone(graph, tile, monkeypatch):
     cases[-1] = (cases[-1][0], cases[-1][1], cases[-1][2].replace(update="jacobi"), cases[-1][3])
     cases.append(_case(90, 40, 2, 8, 0.0, 8))
     cases[-1] = (cases[-1][0], cases[-1][1], cases[-1][2].replace(level_count=0), cases[-1][3])
-    announce("batch vs alone", len(cases), "graph", graph)
+    announce("batch vs alone", len(cases), mode, tile)
     handles = [M.Instance.from_inputs(c[0]) for c in cases]
     alone = [h.solve_ex(R, sch, seed, want_best=True) for h, (_, R, sch, seed) in zip(handles, cases)]
     torch.cuda.synchronize()
@@ -94,9 +106,9 @@ def test_batch_equals_alone(graph, tile, monkeypatch):
         h.close()
 
 
-@pytest.mark.parametrize("graph", ["1", "0"])
-def test_batch_full_and_refusals(graph, monkeypatch):
-    monkeypatch.setenv("MARS_BATCH_GRAPH", graph)
+@pytest.mark.parametrize("mode", list(MODES))
+def test_batch_full_and_refusals(mode, monkeypatch):
+    _mode(mode, monkeypatch)
     M = _mars()
     import torch
 
