@@ -10,7 +10,7 @@ from oracle import oracle as O
 def require_gpu():
     import torch
 
-    assert torch.cuda.is_available(), "GPU tests need a GPU (run them with -m gpu on the GPU box)"
+    assert torch.cuda.is_available(), "GPU tests need a GPU (run them with -m gpu on a machine with an MI355X)"
     return torch
 
 
