@@ -195,174 +195,67 @@ __global__ void k_batch_advance(int *level, BatchCaps c)
     }
 }
 
-// MARS_BATCH_TILE=0|3 in the environment forces the batch's tile shape
-// (128 x 128 / 64 x 64), read per call; -1 when not forced
-int batch_tile_forced()
+hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipStream_t s)
 {
-    const char *fv = std::getenv("MARS_BATCH_TILE");
-    return (fv && (fv[0] == '0' || fv[0] == '3') && !fv[1]) ? fv[0] - '0' : -1;
-}
-
-// tiles of the 128 x 128 shape in phase index ph over the members
-static int batch_tiles128(const BatchMemberDesc *m, int n, int ph)
-{
-    int t128 = 0;
-    for (int i = 0; i < n; ++i)
-        if (ph < m[i].B && m[i].pb[ph + 1] > m[i].pb[ph])
-            t128 += ((m[i].R + 127) / 128) * ((m[i].pb[ph + 1] - m[i].pb[ph] + 127) / 128);
-    return t128;
-}
-
-int batch_phases(const BatchMemberDesc *m, int n)
-{
+    if (n < 1 || n > kMaxBatch)
+        return hipErrorInvalidValue;
+    Bf16BatchArgs a;
+    a.level = level;
     int maxB = 0;
     for (int i = 0; i < n; ++i)
         maxB = std::max(maxB, m[i].B);
-    return maxB;
-}
-
-hipError_t launch_batch_phase(const BatchMemberDesc *m, int n, int *level, int ph, int shape, hipStream_t s)
-{
-    if (n < 1 || n > kMaxBatch)
-        return hipErrorInvalidValue;
-    // tile shape: 128 x 128 (64-deep slabs) when the members' tiles of that
-    // shape fill the chip, else 64 x 64 (four waves, several workgroups per
-    // CU), unless the caller or MARS_BATCH_TILE chose; both reduce every
-    // element in the same order, so results do not depend on the choice
-    const int forced = batch_tile_forced();
-    const bool small = forced >= 0 ? forced == 3 : shape >= 0 ? shape == 3 : batch_tiles128(m, n, ph) < 256;
-    const int bm = small ? 64 : 128, bn = small ? 64 : 128, bk = small ? 64 : HBK;
-    Bf16BatchArgs a;
-    a.level = level;
-    for (int i = 0; i < n; ++i) {
-        const Instance &I = *m[i].I;
-        Bf16BatchMember &d = a.mem[i];
-        d.J = I.Jbf;
-        d.Ma = m[i].Ma;
-        d.Mb = m[i].Mb;
-        d.table = m[i].table;
-        d.hhalf = I.has_h ? I.hhalf : nullptr;
-        d.ldk = I.Np;
-        d.R = m[i].R;
-        d.nrt = (m[i].R + bm - 1) / bm;
-        d.kpad = (I.N + bk - 1) / bk * bk;
-        d.ldt = m[i].ldt;
-        d.kmax = m[i].kmax;
-        d.lslot = m[i].lslot;
-        d.gamma = m[i].gamma;
-    }
-    int ns = 0, tile0 = 0;
-    for (int i = 0; i < n; ++i) {
-        if (ph >= m[i].B || m[i].pb[ph + 1] <= m[i].pb[ph])
-            continue;
-        Bf16BatchSlot &sl = a.slot[ns++];
-        sl.member = i;
-        sl.p0 = m[i].pb[ph];
-        sl.p1 = m[i].pb[ph + 1];
-        sl.nct = (sl.p1 - sl.p0 + bn - 1) / bn;
-        sl.tile0 = tile0;
-        sl.blend = (sl.p0 % 8) != 0;
-        tile0 += (a.mem[i].nrt * sl.nct + 7) / 8 * 8;  // next member starts on a multiple of 8
-    }
-    a.nslot = ns;
-    if (ns == 0)
-        return hipSuccess;
-    if (small)
-        hipLaunchKernelGGL((k_dense_phase_bf16_batch<64, 64, 2, 2, 2, 64>), dim3(tile0), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_dense_phase_bf16_batch<128, 128, 4, 4, 2, HBK>), dim3(tile0), dim3(1024), 0, s, a);
-    return hipGetLastError();
-}
-
-// Batch tile tuner, like the single-instance one: a class is (device,
-// members, 128 x 128 tiles of the first phase in steps of 32, largest N /
-// 1024, capped at 16 and 8).  The first step of a class enqueues, before
-// its sweeps, two launches of the first phase with each shape between timing
-// events (the first phase reads only the previous state, so repeating it
-// changes nothing); a later step of the class reads the events once they
-// have completed and keeps the faster shape for the process.  Until then the
-// tile count decides.  Nothing blocks the host.
-struct BatchTune {
-    bool decided = false;
-    int chosen = -1;
-    hipEvent_t ev[3] = {};
-};
-static std::mutex g_btune_mu;
-static std::map<std::tuple<int, int, int, int>, BatchTune> g_btune;
-
-int batch_tile_choice(const BatchMemberDesc *m, int n, int *level, hipStream_t s)
-{
-    const int forced = batch_tile_forced();
-    if (forced >= 0 || n < 1)
-        return forced;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) {
-        (void)hipGetLastError();
-        return -1;
-    }
-    int maxN = 0;
-    for (int i = 0; i < n; ++i)
-        maxN = std::max(maxN, m[i].I->N);
-    const auto key = std::make_tuple(dev, n, std::min((batch_tiles128(m, n, 0) + 31) / 32, 16),
-                                     std::min((maxN + 1023) / 1024, 8));
-    std::lock_guard<std::mutex> g(g_btune_mu);
-    auto it = g_btune.find(key);
-    if (it != g_btune.end()) {
-        BatchTune &t = it->second;
-        if (t.decided)
-            return t.chosen;
-        const hipError_t q = hipEventQuery(t.ev[2]);
-        if (q != hipSuccess) {
-            if (q == hipErrorNotReady)
-                return -1;
-            (void)hipGetLastError();
-        }
-        float t0 = 0.0f, t1 = 0.0f;
-        if (q == hipSuccess && hipEventElapsedTime(&t0, t.ev[0], t.ev[1]) == hipSuccess &&
-            hipEventElapsedTime(&t1, t.ev[1], t.ev[2]) == hipSuccess)
-            t.chosen = t1 < t0 ? 3 : 0;
-        else
-            (void)hipGetLastError();
-        for (auto &e : t.ev)
-            if (e) {
-                (void)hipEventDestroy(e);
-                e = nullptr;
-            }
-        t.decided = true;
-        return t.chosen;
-    }
-    BatchTune &t = g_btune[key];
-    bool ok = true;
-    for (auto &e : t.ev)
-        ok = ok && hipEventCreate(&e) == hipSuccess;
-    ok = ok && hipEventRecord(t.ev[0], s) == hipSuccess;
-    for (int r = 0; ok && r < 2; ++r)
-        ok = launch_batch_phase(m, n, level, 0, 0, s) == hipSuccess;
-    ok = ok && hipEventRecord(t.ev[1], s) == hipSuccess;
-    for (int r = 0; ok && r < 2; ++r)
-        ok = launch_batch_phase(m, n, level, 0, 3, s) == hipSuccess;
-    ok = ok && hipEventRecord(t.ev[2], s) == hipSuccess;
-    if (!ok) {
-        // timing unavailable: the tile count decides for this class
-        (void)hipGetLastError();
-        for (auto &e : t.ev)
-            if (e) {
-                (void)hipEventDestroy(e);
-                e = nullptr;
-            }
-        t.decided = true;
-        t.chosen = -1;
-    }
-    return -1;
-}
-
-hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, int shape, hipStream_t s)
-{
-    if (n < 1 || n > kMaxBatch)
-        return hipErrorInvalidValue;
-    const int maxB = batch_phases(m, n);
+    // tile shape of a phase launch: 128 x 128 (128-deep slabs) when the
+    // members' tiles of that shape fill the chip, else 64 x 64 (four waves,
+    // several workgroups per CU); both reduce every element in the same order,
+    // so results do not depend on the choice.  MARS_BATCH_TILE=0|3 forces one.
+    const char *fv = std::getenv("MARS_BATCH_TILE");
+    const int forced = (fv && (fv[0] == '0' || fv[0] == '3') && !fv[1]) ? fv[0] - '0' : -1;
     for (int ph = 0; ph < maxB; ++ph) {
-        const hipError_t e = launch_batch_phase(m, n, level, ph, shape, s);
+        int t128 = 0;
+        for (int i = 0; i < n; ++i)
+            if (ph < m[i].B && m[i].pb[ph + 1] > m[i].pb[ph])
+                t128 += ((m[i].R + 127) / 128) * ((m[i].pb[ph + 1] - m[i].pb[ph] + 127) / 128);
+        const bool small = forced >= 0 ? forced == 3 : t128 < 256;
+        const int bm = small ? 64 : 128, bn = small ? 64 : 128, bk = small ? 64 : HBK;
+        for (int i = 0; i < n; ++i) {
+            const Instance &I = *m[i].I;
+            Bf16BatchMember &d = a.mem[i];
+            d.J = I.Jbf;
+            d.Ma = m[i].Ma;
+            d.Mb = m[i].Mb;
+            d.table = m[i].table;
+            d.hhalf = I.has_h ? I.hhalf : nullptr;
+            d.ldk = I.Np;
+            d.R = m[i].R;
+            d.nrt = (m[i].R + bm - 1) / bm;
+            d.kpad = (I.N + bk - 1) / bk * bk;
+            d.ldt = m[i].ldt;
+            d.kmax = m[i].kmax;
+            d.lslot = m[i].lslot;
+            d.gamma = m[i].gamma;
+        }
+        int ns = 0, tile0 = 0;
+        for (int i = 0; i < n; ++i) {
+            if (ph >= m[i].B || m[i].pb[ph + 1] <= m[i].pb[ph])
+                continue;
+            Bf16BatchSlot &sl = a.slot[ns++];
+            sl.member = i;
+            sl.p0 = m[i].pb[ph];
+            sl.p1 = m[i].pb[ph + 1];
+            sl.nct = (sl.p1 - sl.p0 + bn - 1) / bn;
+            sl.tile0 = tile0;
+            sl.blend = (sl.p0 % 8) != 0;
+            tile0 += (a.mem[i].nrt * sl.nct + 7) / 8 * 8;  // next member starts on a multiple of 8
+        }
+        a.nslot = ns;
+        if (ns == 0)
+            continue;
+        if (small)
+            hipLaunchKernelGGL((k_dense_phase_bf16_batch<64, 64, 2, 2, 2, 64>), dim3(tile0), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_dense_phase_bf16_batch<128, 128, 4, 4, 2, HBK>), dim3(tile0), dim3(1024), 0, s,
+                               a);
+        const hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
@@ -402,24 +295,30 @@ static hipError_t launch_persistent_shape(Bf16BatchPersistArgs &a, int widest, h
 
 static_assert(sizeof(Bf16BatchPersistArgs) <= 4096, "persistent step descriptors travel as kernel arguments");
 
-hipError_t launch_batch_persistent(const BatchMemberDesc *m, int n, int *level, int sweeps, int shape, hipStream_t s)
+hipError_t launch_batch_persistent(const BatchMemberDesc *m, int n, int *level, int sweeps, hipStream_t s)
 {
     if (n < 1 || n > kMaxBatch || sweeps < 1)
         return hipErrorInvalidValue;
-    const int maxB = batch_phases(m, n);
+    int maxB = 0;
+    for (int i = 0; i < n; ++i)
+        maxB = std::max(maxB, m[i].B);
     if (maxB > kMaxPersistPhases)
         return hipErrorNotSupported;
-    // one tile shape for the step: the caller's or MARS_BATCH_TILE's choice,
-    // else 128 x 128 when every phase's tiles of that shape fill the chip and
-    // 64 x 64 otherwise (bitwise the same results either way)
+    // one tile shape for the step: 128 x 128 when every phase's tiles of that
+    // shape fill the chip, else 64 x 64 (bitwise the same results either way);
+    // MARS_BATCH_TILE=0|3 forces one
+    const char *fv = std::getenv("MARS_BATCH_TILE");
+    const int forced = (fv && (fv[0] == '0' || fv[0] == '3') && !fv[1]) ? fv[0] - '0' : -1;
     int t128min = 1 << 30;
     for (int ph = 0; ph < maxB; ++ph) {
-        const int t128 = batch_tiles128(m, n, ph);
+        int t128 = 0;
+        for (int i = 0; i < n; ++i)
+            if (ph < m[i].B && m[i].pb[ph + 1] > m[i].pb[ph])
+                t128 += ((m[i].R + 127) / 128) * ((m[i].pb[ph + 1] - m[i].pb[ph] + 127) / 128);
         if (t128 > 0)
             t128min = std::min(t128min, t128);
     }
-    const int forced = batch_tile_forced();
-    const bool small = forced >= 0 ? forced == 3 : shape >= 0 ? shape == 3 : t128min < 256;
+    const bool small = forced >= 0 ? forced == 3 : t128min < 256;
     const int bm = small ? 64 : 128, bn = small ? 64 : 128, bk = small ? 64 : HBK;
     Bf16BatchPersistArgs a;
     a.level = level;

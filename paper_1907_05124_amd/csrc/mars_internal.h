@@ -272,29 +272,16 @@ struct BatchMemberDesc {
     float gamma;
 };
 constexpr int kMaxBatchMembers = 16;
-// Tile shape of the batch's phase launches: 0 = 128 x 128, 3 = 64 x 64, -1 =
-// chosen from the members' tile count (MARS_BATCH_TILE=0|3 in the
-// environment overrides every choice; batch_tile_forced returns it or -1).
-// Results do not depend on the shape.
-int batch_tile_forced();
-int batch_phases(const BatchMemberDesc *m, int n);
-// The measured shape for the members' class, or -1 while it is being timed
-// (the first call of a class enqueues the timing launches on s).
-int batch_tile_choice(const BatchMemberDesc *m, int n, int *level, hipStream_t s);
-// One phase index of the members: one launch over the tiles of every member
-// that has that phase (a phase only rewrites its own rows from the previous
-// state, so it can be repeated, e.g. to time the shapes).
-hipError_t launch_batch_phase(const BatchMemberDesc *m, int n, int *level, int ph, int shape, hipStream_t s);
-// One sweep of the members: launch_batch_phase for each phase index, then the
-// level advance (level[lslot] += 1 below kmax).  Kernel launches only, so it
-// can be captured in a graph.
-hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, int shape, hipStream_t s);
+// One sweep of the members: one launch per phase index over the tiles of
+// every member that has that phase, then the level advance (level[lslot] += 1
+// below kmax).  Kernel launches only, so it can be captured in a graph.
+hipError_t launch_batch_sweep(const BatchMemberDesc *m, int n, int *level, hipStream_t s);
 // `sweeps` sweeps of the members as one persistent cooperative launch (grid
 // barriers between phases, the level counters advanced on the device),
 // bitwise the same as that many launch_batch_sweep calls;
 // hipErrorNotSupported when a member has more phases than the launch's
 // descriptors hold.
-hipError_t launch_batch_persistent(const BatchMemberDesc *m, int n, int *level, int sweeps, int shape, hipStream_t s);
+hipError_t launch_batch_persistent(const BatchMemberDesc *m, int n, int *level, int sweeps, hipStream_t s);
 void launch_bf16_round(const unsigned short *MT, int ldk, int N, int R, int Ke, int8_t *spad, int8_t *spins,
                        float *m_final, hipStream_t s);
 

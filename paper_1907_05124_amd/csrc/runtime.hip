@@ -1181,7 +1181,6 @@ struct Batch {
     bool graphs = true;
     hipGraphExec_t exec = nullptr;
     int exec_sweeps = 0;
-    int exec_shape = -1;  // tile shape the graph was captured with
     // the whole step as one persistent cooperative launch (members with at
     // most four phases; otherwise the graph or eager path).  Off by default:
     // its grid barriers measured slower than replaying the per-phase launches
@@ -1329,11 +1328,8 @@ static mars_status batch_step(Batch &b, int sweeps, int64_t *tags, int cap, int 
     BatchMemberDesc dm[kMaxBatchMembers];
     describe(b, dm);
     const int n = (int)b.members.size();
-    // tile shape: measured per class of memberships (timing launches are
-    // enqueued here, outside any capture, by the first step of a class)
-    const int shape = batch_tile_choice(dm, n, b.level, b.s);
     if (b.persist) {
-        const hipError_t e = launch_batch_persistent(dm, n, b.level, sweeps, shape, b.s);
+        const hipError_t e = launch_batch_persistent(dm, n, b.level, sweeps, b.s);
         if (e == hipSuccess) {
             for (BatchMember &m : b.members)
                 m.k = std::min(m.k + sweeps, m.d.kmax);
@@ -1345,13 +1341,13 @@ static mars_status batch_step(Batch &b, int sweeps, int64_t *tags, int cap, int 
     }
     if (b.graphs && b.s) {
         // the whole step as one graph launch, captured once per membership
-        if (!b.exec || b.exec_sweeps != sweeps || b.exec_shape != shape) {
+        if (!b.exec || b.exec_sweeps != sweeps) {
             drop_graph(b);
             hipGraph_t g = nullptr;
             MARS_HIP(hipStreamBeginCapture(b.s, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
             for (int sw = 0; sw < sweeps && e == hipSuccess; ++sw)
-                e = launch_batch_sweep(dm, n, b.level, shape, b.s);
+                e = launch_batch_sweep(dm, n, b.level, b.s);
             const hipError_t e2 = hipStreamEndCapture(b.s, &g);
             if (e == hipSuccess)
                 e = e2;
@@ -1364,7 +1360,6 @@ static mars_status batch_step(Batch &b, int sweeps, int64_t *tags, int cap, int 
                 return hip_error(e, "capturing the batch step");
             }
             b.exec_sweeps = sweeps;
-            b.exec_shape = shape;
         }
         MARS_HIP(hipGraphLaunch(b.exec, b.s));
         for (BatchMember &m : b.members)
@@ -1380,7 +1375,7 @@ static mars_status batch_step(Batch &b, int sweeps, int64_t *tags, int cap, int 
             any |= m.k < m.d.kmax;
         if (!any)
             break;
-        hipError_t e = launch_batch_sweep(dm, nm, b.level, shape, b.s);
+        hipError_t e = launch_batch_sweep(dm, nm, b.level, b.s);
         if (e != hipSuccess)
             return hip_error(e, "batch sweep launch");
         for (BatchMember &m : b.members)
