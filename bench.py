@@ -43,28 +43,28 @@ KERNEL_SOURCES = {
 }
 TRAFFIC_RECORD = {
     ("sk2000", "fp32"): {"kernel": "k_dense_phase_f32", "sha256_prefix": "5e141b5bb4edf753",
-        "fetch_kib": 60401.4, "write_kib": 27264.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 60399.2, "write_kib": 27264.0, "fetch_scale": 2.0, "write_scale": 1.0,
         "summary": "profiles/k_dense_phase_f32_sk2000.md"},
-    ("sk2000", "bf16"): {"kernel": "k_dense_phase_bf16", "sha256_prefix": "69d973aab5933def",
-        "fetch_kib": 26426.7, "write_kib": 8256.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    ("sk2000", "bf16"): {"kernel": "k_dense_phase_bf16", "sha256_prefix": "abd9cf6588efd30d",
+        "fetch_kib": 26429.7, "write_kib": 8256.0, "fetch_scale": 2.0, "write_scale": 1.0,
         "summary": "profiles/k_dense_phase_bf16_sk2000.md"},
     ("er800", "fp32"): {"kernel": "k_sparse_solve", "sha256_prefix": "5c4273a474ee9f48",
-        "fetch_kib": 1211.2, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 1210.9, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
         "summary": "profiles/k_sparse_solve_er800.md"},
     ("er800", "fp16"): {"kernel": "k_sparse_solve", "sha256_prefix": "5c4273a474ee9f48",
-        "fetch_kib": 1210.3, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 1210.9, "write_kib": 6656.0, "fetch_scale": 2.0, "write_scale": 1.0,
         "summary": "profiles/k_sparse_solve_er800.md"},
     ("er20000", "fp16"): {"kernel": "k_sparse_solve", "sha256_prefix": "5c4273a474ee9f48",
-        "fetch_kib": 3421.5, "write_kib": 164555.9, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 3424.0, "write_kib": 165309.7, "fetch_scale": 2.0, "write_scale": 1.0,
         "summary": "profiles/k_sparse_solve_er20000.md"},
     ("ea2d_L16", "fp64"): {"kernel": "k_lattice_solve", "sha256_prefix": "cbc9d812e2337556",
         "fetch_kib": 115.2, "write_kib": 288.0, "fetch_scale": 2.0, "write_scale": 1.0,
         "summary": "profiles/k_lattice_solve_ea2d_L16.md"},
     ("ea2d_L16", "fp32"): {"kernel": "k_lattice_solve", "sha256_prefix": "cbc9d812e2337556",
-        "fetch_kib": 111.8, "write_kib": 288.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 111.9, "write_kib": 288.0, "fetch_scale": 2.0, "write_scale": 1.0,
         "summary": "profiles/k_lattice_solve_ea2d_L16.md"},
     ("ea3d_L32", "fp16"): {"kernel": "k_lattice_solve", "sha256_prefix": "cbc9d812e2337556",
-        "fetch_kib": 1031.9, "write_kib": 65600.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "fetch_kib": 1030.6, "write_kib": 65600.0, "fetch_scale": 2.0, "write_scale": 1.0,
         "summary": "profiles/k_lattice_solve_ea3d_L32.md"},
 }
 
