@@ -139,13 +139,15 @@ static void acc_normalise(orc_acc *a)
     int64_t carry = 0;
     for (int q = 0; q < ACC_DIGITS; ++q) {
         int64_t v = a->d[q] + carry;
-        /* floor division by 2^32 */
+        /* floor division by 2^32 (gcc shifts signed values arithmetically);
+         * the products below stay within int64 (|c| < 2^31) and, unlike a
+         * left shift of a negative value, are defined C */
         int64_t c = v >> 32;
-        a->d[q] = v - (c << 32);
+        a->d[q] = v - c * ((int64_t)1 << 32);
         carry = c;
     }
     /* the top digit keeps the sign: fold the final carry back in */
-    a->d[ACC_DIGITS - 1] += carry << 32;
+    a->d[ACC_DIGITS - 1] += carry * ((int64_t)1 << 32);
     a->pending = 0;
 }
 
