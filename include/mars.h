@@ -56,7 +56,9 @@ typedef enum {
     MARS_E_DIAGONAL = 3,     /* nonzero J_ii, or a self loop in CSR */
     MARS_E_NONFINITE = 4,    /* NaN or infinity in J or h */
     MARS_E_RANGE = 5,        /* exact energy would need more than 126 bits */
-    MARS_E_OOM = 6,          /* device allocation failed */
+    MARS_E_OOM = 6,          /* device allocation failed (also every instance and workspace
+                                allocation while MARS_TEST_FAIL_ALLOC=1 is set in the
+                                environment: a test hook for the error paths) */
     MARS_E_DEVICE = 7,       /* HIP runtime error or no usable gfx950 device */
     MARS_E_UNSUPPORTED = 8   /* valid request outside what this build implements */
 } mars_status;

@@ -34,6 +34,16 @@ mars_status hip_error(hipError_t e, const char *what)
     return set_error(MARS_E_DEVICE, m);
 }
 
+// Test hook: with MARS_TEST_FAIL_ALLOC=1 in the environment (read at each
+// allocation) every device allocation of the library's instances and
+// workspaces fails as out of memory, so that tests can drive the error paths
+// of creation and of solves.
+static bool injected_alloc_failure()
+{
+    const char *f = std::getenv("MARS_TEST_FAIL_ALLOC");
+    return f && f[0] == '1' && !f[1];
+}
+
 mars_status ensure(DevBuf &b, size_t bytes)
 {
     if (bytes == 0)
@@ -47,6 +57,8 @@ mars_status ensure(DevBuf &b, size_t bytes)
         if (e != hipSuccess)
             return hip_error(e, "hipFree");
     }
+    if (injected_alloc_failure())
+        return set_error(MARS_E_OOM, "workspace allocation refused (MARS_TEST_FAIL_ALLOC)");
     hipError_t e = hipMalloc(&b.p, bytes);
     if (e != hipSuccess) {
         b.p = nullptr;
@@ -70,6 +82,8 @@ static mars_status dev_alloc(T **p, size_t count)
     *p = nullptr;
     if (count == 0)
         count = 1;
+    if (injected_alloc_failure())
+        return set_error(MARS_E_OOM, "device allocation refused (MARS_TEST_FAIL_ALLOC)");
     hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
     if (e != hipSuccess) {
         *p = nullptr;
